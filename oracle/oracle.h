@@ -1,0 +1,84 @@
+/*
+ * CPU oracle for the checkerboard Metropolis sweep of the 2D Ising and
+ * Blume-Capel models and for the measurements taken during the relaxation
+ * after a quench (Bisson et al., "Massive-Scale Simulations of 2D Ising and
+ * Blume-Capel Models on Rack-Scale Multi-GPU Systems", arXiv:2502.18624).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path
+ * (the HIP library and its Python binding) never links, imports or calls it.
+ * It shares no code, header, table or constant generator with the product.
+ *
+ * Plain, slow, obviously correct: an int8 array s[y*L + x] with x the fast
+ * axis, periodic boundaries, scalar loops, fp64 on the host for the
+ * acceptance thresholds.  Each function cites the passage of the paper that
+ * defines what it computes; where the paper is silent the reading taken is
+ * stated next to the function (and listed with the other readings in the
+ * design notes of the repository).
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_ISING = 0, ORA_BC = 1 };
+enum { ORA_INIT_RANDOM = 0, ORA_INIT_UP = 1, ORA_INIT_DOWN = 2, ORA_INIT_ZERO = 3 };
+enum { ORA_CORR_FULL = 1, ORA_CORR_PROTOCOL = 2 };
+
+/* Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11); the
+ * paper draws its uniforms from this generator (section 3.2). */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The three random streams of the counter contract (reading of the paper's
+ * unstated RNG layout; all keyed by the logical site, never by storage). */
+uint32_t ora_accept_draw(uint64_t seed, uint32_t t, int color, uint64_t k);
+int      ora_proposal_bit(uint64_t seed, uint32_t t, int color, uint64_t k);
+uint32_t ora_init_draw(uint64_t seed, uint64_t n);
+
+/* Acceptance threshold floor(2^32 exp(-beta dE)) clamped to 2^32-1, dE > 0. */
+uint32_t ora_threshold(double beta, double dE);
+
+/* Probability with which the oracle's update rule accepts a move; for the
+ * Ising model `aligned` is the number of neighbours equal to the spin (the
+ * section 3.2 rule), for Blume-Capel (s, h, b) give the proposal. */
+double ora_ising_flip_prob(int aligned, double beta);
+double ora_bc_accept_prob(int s, int h, int b, double beta, double D);
+
+int  ora_init(int8_t* s, int model, int64_t L, uint64_t seed, int init_state);
+
+/* n sweeps starting at sweep index t0.  If dB/dQ are non-NULL they
+ * accumulate the bond-sum and sum-of-squares changes of every accepted move.
+ * nthreads > 1 splits the rows of one colour over OpenMP threads (even L). */
+int  ora_sweep(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0,
+               int64_t n, double beta, double D, int nthreads,
+               int64_t* dB, int64_t* dQ);
+
+/* B = sum s(x,y)[s(x+1,y)+s(x,y+1)], M = sum s, Q = sum s^2, counts of -1,0,+1. */
+void ora_measure(const int8_t* s, int64_t L, int64_t* B, int64_t* M, int64_t* Q,
+                 int64_t counts[3]);
+
+/* Distances of the correlation function (section 3.3).  Returns the number
+ * of distances, or -(needed) if cap is too small. */
+int  ora_rset(int mode, int64_t L, int64_t t, int32_t* r, int cap);
+int64_t ora_rc(int64_t L, int64_t t);
+double  ora_g(int64_t L);
+
+/* S_a(r) = sum over sources p of s(p) s(p + r e_a), a in {x, y}. */
+void ora_corr(const int8_t* s, int64_t L, int mode, const int32_t* r, int nr,
+              int64_t* Cx, int64_t* Cy, int64_t* nsrc);
+
+/* Schwinger-Dyson histogram: hist[k] = #sites with sigma*h = k - 4. */
+void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9]);
+
+/* Runs n sweeps one at a time and records B, M, Q after each. */
+int  ora_series(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0, int64_t n,
+                double beta, double D, int64_t* Bs, int64_t* Ms, int64_t* Qs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
