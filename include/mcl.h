@@ -1,0 +1,176 @@
+/*
+ * mcl.h -- C ABI of the MI355X (gfx950) library for the checkerboard
+ * Metropolis sweep of the 2D Ising and Blume-Capel models and the
+ * measurements taken while the lattice relaxes after a quench
+ * (Bisson et al., arXiv:2502.18624).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: MCL_OK (0) or a negative MCL_E*
+ *    code; nothing throws across the ABI.  mcl_strerror() names a code and
+ *    mcl_last_hip_error() returns the HIP error behind the last MCL_EHIP.
+ *  - Units J = k_B = 1 (section 3.2 states the Ising flip probabilities as
+ *    e^{-4 beta} and e^{-8 beta}); beta = 1/T.  The energy of eq. (BC) is
+ *    E = -B + D Q with the integer sums returned by measure(); for the
+ *    Ising model (eq. IM) E = -B.
+ *  - The lattice is L x L, periodic, site (x, y) with x the fast axis; its
+ *    colour is (x + y) & 1 (checkerboard decomposition, section 3.1) and a
+ *    sweep updates colour 0, then colour 1.  L must be a multiple of 64 and
+ *    at least 64.
+ *  - Randomness is counter-based Philox4x32-10 keyed by the 64-bit seed and
+ *    addressed by (sweep t, colour, logical site), so results do not depend
+ *    on storage layout, batching or launch shape: every lattice is
+ *    bit-reproducible.  Counter words, per stream:
+ *      accept draw  : k = (y L + x) >> 1; ctr = (k>>2 lo, k>>2 hi, t, c),
+ *                     output word k & 3
+ *      proposal bit : ctr = (k>>7 lo, k>>7 hi, t, 2 + c), bit k & 31 of
+ *                     output word (k >> 5) & 3               (Blume-Capel)
+ *      initial draw : n = y L + x; ctr = (n>>2 lo, n>>2 hi, 0, 4), word n & 3
+ *  - Acceptance is integer: a move raising the energy by dE > 0 is accepted
+ *    iff u < floor(2^32 exp(-beta dE)) (clamped to 2^32 - 1), u the accept
+ *    draw; dE <= 0 is always accepted.
+ *  - Device memory is owned by the caller: lattice_init() receives one
+ *    device buffer of at least mcl_query_bytes() bytes and keeps a
+ *    non-owning pointer to it until lattice_free().  Handles are owned by
+ *    the library.  Host buffers passed in are owned by the caller and only
+ *    read/written during the call.
+ *  - Work is queued on the caller's HIP stream (hipStream_t passed as
+ *    void*; NULL = the null stream).  sweep() and group_sweep() are
+ *    asynchronous; measure(), lattice_read*() and lattice_write()
+ *    synchronise that stream before returning.
+ *  - One handle must not be used from two threads at once; distinct
+ *    handles are independent.
+ */
+#ifndef MCL_H
+#define MCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcl_lattice mcl_lattice;
+
+/* Models: eq. (IM), spins +-1; eq. (BC), spins -1/0/+1 with crystal field D. */
+enum { MCL_ISING = 0, MCL_BC = 1 };
+
+/* Initial states.  RANDOM is the T = infinity sample that a quench starts
+ * from (section 1): Ising s = +1 iff w < 2^31, Blume-Capel
+ * s = floor(3 w / 2^32) - 1, w the initial draw.  ZERO is Blume-Capel only. */
+enum { MCL_INIT_RANDOM = 0, MCL_INIT_UP = 1, MCL_INIT_DOWN = 2, MCL_INIT_ZERO = 3 };
+
+/* Correlation modes of measure() (section 3.3).
+ *   FULL     : every distance 0..L/2 from every site.
+ *   PROTOCOL : every site for r <= 2R = 32; one source per R x R square
+ *              (x = y = 0 mod 16) for 32 < r <= r_c(t) and for the
+ *              log-spaced distances floor(2^{x/32}) > r_c(t) up to L/2, with
+ *              r_c(t) = max{256, floor(g(L) sqrt(t) + 0.5)} and
+ *              g(L) = 6 sqrt(ln(L / 2^16) / 3.3^2 + 1).  L a power of two. */
+enum { MCL_CORR_NONE = 0, MCL_CORR_FULL = 1, MCL_CORR_PROTOCOL = 2 };
+
+enum {
+    MCL_OK = 0,
+    MCL_EMODEL = -1,    /* unknown model */
+    MCL_EL = -2,        /* L not a multiple of 64, or < 64 (or PROTOCOL with L not 2^k) */
+    MCL_EBETA = -3,     /* beta NaN or negative (beta = +inf is allowed) */
+    MCL_ED = -4,        /* D NaN */
+    MCL_EINIT = -5,     /* unknown init state, or ZERO with the Ising model */
+    MCL_ENOMEM = -6,    /* dev_bytes smaller than mcl_query_bytes() */
+    MCL_ERANGE = -7,    /* the sweep counter t would pass 2^32 - 1; bad window */
+    MCL_EHIP = -8,      /* a HIP call failed: see mcl_last_hip_error() */
+    MCL_EARG = -9,      /* NULL pointer, negative count, unknown mode */
+    MCL_EBUFSZ = -10,   /* caller buffer too small; the needed size is reported */
+    MCL_ESPINS = -11    /* lattice_write() got a value outside the model's spins */
+};
+
+/* Output of measure().  The caller owns the arrays r, Cx, Cy, nsrc (r_cap
+ * entries each; they may be NULL when corr_mode is MCL_CORR_NONE). */
+typedef struct mcl_measure_out {
+    int64_t B;          /* sum over sites of s(x,y) [s(x+1,y) + s(x,y+1)] */
+    int64_t M;          /* sum of s */
+    int64_t Q;          /* sum of s^2 */
+    int64_t t;          /* sweeps completed */
+    int64_t counts[3];  /* number of spins equal to -1, 0, +1 */
+    int64_t invalid;    /* stored cells that hold no spin value; 0 unless corrupted */
+    int32_t* r;         /* out: distances */
+    int64_t* Cx;        /* out: sum over sources p of s(p) s(p + r e_x) */
+    int64_t* Cy;        /* out: sum over sources p of s(p) s(p + r e_y) */
+    int64_t* nsrc;      /* out: number of sources at each distance */
+    int32_t r_cap;      /* in: capacity of the four arrays */
+    int32_t n_r;        /* out: number of distances (also set on MCL_EBUFSZ) */
+} mcl_measure_out;
+
+/* Device bytes lattice_init() needs for an L x L lattice of `model`: two
+ * colour planes of 4-bit cells (L^2 / 2 bytes) plus measurement scratch. */
+int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes);
+
+/* a1 -- Create a handle and write the initial state (section 1: quench
+ * from a high temperature; see MCL_INIT_*).  dev_mem: caller-owned device
+ * buffer of dev_bytes >= mcl_query_bytes(); hip_stream: stream for all of
+ * this handle's work.  The sweep counter t starts at 0. */
+int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int init_state,
+                 void* dev_mem, int64_t dev_bytes, void* hip_stream);
+
+/* a2..a5 -- n checkerboard sweeps (section 3.1: colour 0, then colour 1)
+ * of single-spin Metropolis updates (section 1) at inverse temperature beta
+ * and crystal field D (ignored for Ising).  Ising: a spin with 3 aligned
+ * neighbours flips with probability e^{-4 beta}, with 4 with e^{-8 beta},
+ * otherwise always (section 3.2).  Blume-Capel: the proposal is one of the
+ * two other values, chosen by the proposal bit (0: next value cyclically in
+ * -1,0,+1; 1: the one after), accepted by Metropolis on eq. (BC).
+ * Asynchronous on the handle's stream; advances t by n. */
+int sweep(mcl_lattice* h, int64_t n, double beta, double D);
+
+/* a6..a8 -- B, M, Q, spin counts and, if corr_mode != NONE, the
+ * correlation sums along both axes at the distances of the mode for the
+ * current t (section 3.3).  Synchronous.  MCL_EBUFSZ if r_cap < needed
+ * (out->n_r then holds the needed size). */
+int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out);
+
+/* Distances measure() would use for (mode, L, t); returns their number or
+ * MCL_EBUFSZ (with *n_needed set) if cap is too small. */
+int mcl_rset(int corr_mode, int64_t L, int64_t t, int32_t* r, int32_t cap, int32_t* n_needed);
+
+/* The acceptance thresholds sweep() uses.  Ising: thr[0] = floor(2^32
+ * e^{-4 beta}), thr[1] = floor(2^32 e^{-8 beta}), always[] unused.
+ * Blume-Capel: 54 entries indexed ((s+1)*2 + b)*9 + (h+4); always[i] = 1
+ * where dE <= 0.  dE = -h (s' - s) + D (s'^2 - s^2) in double, that order. */
+int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* always, int32_t cap);
+
+/* Copy the lattice to host memory as L*L int8 spins, row-major [y][x].
+ * Synchronous.  Used for parity checks and checkpoints. */
+int lattice_read(mcl_lattice* h, int8_t* host_spins);
+
+/* Window [x0, x0+w) x [y0, y0+hgt) (periodic) as w*hgt int8 spins. */
+int lattice_read_window(mcl_lattice* h, int64_t x0, int64_t y0, int64_t w, int64_t hgt,
+                        int8_t* host_spins);
+
+/* Raw colour planes (both, plane 0 first, mcl_query_bytes layout);
+ * bytes must be >= L*L/2.  For checkpoints of large lattices. */
+int lattice_read_packed(mcl_lattice* h, void* host, int64_t bytes);
+int lattice_write_packed(mcl_lattice* h, const void* host, int64_t bytes, int64_t t);
+
+/* Restore: L*L int8 spins (valid for the model) and the sweep counter t. */
+int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t);
+
+/* Handle state. */
+int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, int64_t* t);
+
+/* a9 -- Batched path: advance `count` independent lattices (any mix of
+ * models, sizes, beta and D) by n[i] sweeps each.  All lattices must share
+ * the stream of hs[0].  Replicas advance sweep by sweep together; every
+ * lattice ends bit-identical to n[i] sweep() calls on it alone. */
+int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n,
+                const double* beta, const double* D);
+
+/* Release a handle (does not free the caller's device memory). */
+int lattice_free(mcl_lattice* h);
+
+const char* mcl_strerror(int code);
+int mcl_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCL_H */

@@ -1,0 +1,448 @@
+// C ABI of the library (declared in include/mcl.h): handles, argument
+// checks, host-side acceptance tables and correlation distances, and the
+// plain one-lattice-per-launch sweep driver (row a5).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mcl.h"
+#include "internal.h"
+
+struct mcl_lattice {
+    int model;
+    int64_t L;
+    uint64_t seed;
+    int64_t t;
+    mcl::Geom g;
+    int64_t* acc;        // device: kAccSlots int64
+    int32_t* rdev;       // device: distances, rcap entries
+    int64_t* Cx;         // device: rcap entries
+    int64_t* Cy;         // device: rcap entries
+    int64_t rcap;
+    hipStream_t stream;
+};
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return MCL_EHIP;
+}
+
+#define MCL_HIP(call)                                  \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_);     \
+    } while (0)
+
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+bool valid_L(int64_t L) { return L >= 64 && (L % 64) == 0 && L <= (int64_t(1) << 20); }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+struct Layout {
+    int64_t planes, acc, rlist, cx, cy, total, rcap;
+};
+
+Layout layout_of(int64_t L)
+{
+    Layout lay;
+    lay.rcap = L / 2 + 1;
+    int64_t off = 0;
+    lay.planes = off;
+    off += align256(L * L / 2);
+    lay.acc = off;
+    off += align256(mcl::kAccSlots * 8);
+    lay.rlist = off;
+    off += align256(lay.rcap * 4);
+    lay.cx = off;
+    off += align256(lay.rcap * 8);
+    lay.cy = off;
+    off += align256(lay.rcap * 8);
+    lay.total = off;
+    return lay;
+}
+
+// floor(2^32 exp(-beta dE)) clamped to 2^32 - 1, for dE > 0 (the integer
+// form of the Metropolis acceptance probability).
+uint32_t threshold_of(double beta, double dE)
+{
+    const double scaled = std::ldexp(std::exp(-beta * dE), 32);
+    if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)std::floor(scaled);
+}
+
+void ising_thresholds(double beta, uint32_t& T4, uint32_t& T8)
+{
+    T4 = threshold_of(beta, 4.0);   // three aligned neighbours: dE = 4
+    T8 = threshold_of(beta, 8.0);   // four aligned neighbours:  dE = 8
+}
+
+// Blume-Capel: entry ((n * 2) + b) * 9 + hsum with n = s + 1, hsum = h + 4;
+// proposal s' = ((n + 1 + b) mod 3) - 1; dE of eq. (BC) with J = 1.
+void bc_table(double beta, double D, mcl::BCTable& tb)
+{
+    for (int n = 0; n < 3; ++n)
+        for (int b = 0; b < 2; ++b)
+            for (int hsum = 0; hsum < 9; ++hsum) {
+                const int s = n - 1, h = hsum - 4;
+                const int s2 = ((n + 1 + b) % 3) - 1;
+                const double dE = (double)(-h * (s2 - s)) + D * (double)(s2 * s2 - s * s);
+                const int idx = (n * 2 + b) * 9 + hsum;
+                if (dE <= 0.0) {
+                    tb.always[idx] = 1;
+                    tb.thr[idx] = 0;
+                } else {
+                    tb.always[idx] = 0;
+                    tb.thr[idx] = threshold_of(beta, dE);
+                }
+            }
+}
+
+// Correlation distances (section 3.3); returns them sorted ascending with
+// the count of leading "every source" distances in n_all.
+std::vector<int32_t> distances(int mode, int64_t L, int64_t t, int32_t* n_all)
+{
+    std::vector<int32_t> r;
+    const int64_t half = L / 2;
+    if (mode == MCL_CORR_FULL) {
+        for (int64_t v = 0; v <= half; ++v) r.push_back((int32_t)v);
+        if (n_all) *n_all = (int32_t)r.size();
+        return r;
+    }
+    const int64_t R2 = 32;
+    const double g = 6.0 * std::sqrt(std::log((double)L / 65536.0) / (3.3 * 3.3) + 1.0);
+    int64_t rc = (int64_t)std::floor(g * std::sqrt((double)t) + 0.5);
+    if (rc < 256) rc = 256;
+    for (int64_t v = 0; v <= std::min(half, R2); ++v) r.push_back((int32_t)v);
+    if (n_all) *n_all = (int32_t)r.size();
+    for (int64_t v = R2 + 1; v <= std::min(half, rc); ++v) r.push_back((int32_t)v);
+    int64_t lg = 0;
+    while ((int64_t(1) << lg) < L) ++lg;
+    const int64_t xmax = 32 * (lg - 1);
+    for (int64_t x = 1; x <= xmax; ++x) {
+        const int64_t d = (int64_t)std::floor(std::pow(2.0, (double)x / 32.0));
+        if (d > rc && d <= half && (r.empty() || r.back() != d)) r.push_back((int32_t)d);
+    }
+    return r;
+}
+
+int check_params(const mcl_lattice* h, double beta, double D)
+{
+    if (std::isnan(beta) || beta < 0.0) return MCL_EBETA;
+    if (h->model == MCL_BC && std::isnan(D)) return MCL_ED;
+    return MCL_OK;
+}
+
+int8_t cell_to_spin(uint32_t word, int64_t i) { return (int8_t)((int)((word >> (4 * (i & 7))) & 0xFu) - 1); }
+
+}  // namespace
+
+extern "C" {
+
+const char* mcl_strerror(int code)
+{
+    switch (code) {
+    case MCL_OK: return "ok";
+    case MCL_EMODEL: return "unknown model";
+    case MCL_EL: return "L must be a multiple of 64 in [64, 2^20] (a power of two for the protocol)";
+    case MCL_EBETA: return "beta must be >= 0 (NaN rejected)";
+    case MCL_ED: return "D must not be NaN";
+    case MCL_EINIT: return "unknown initial state for this model";
+    case MCL_ENOMEM: return "device buffer smaller than mcl_query_bytes()";
+    case MCL_ERANGE: return "value out of range (sweep counter or window)";
+    case MCL_EHIP: return "HIP runtime error (see mcl_last_hip_error)";
+    case MCL_EARG: return "invalid argument";
+    case MCL_EBUFSZ: return "caller buffer too small";
+    case MCL_ESPINS: return "spin value not allowed for this model";
+    default: return "unknown error";
+    }
+}
+
+int mcl_last_hip_error(void) { return g_last_hip; }
+
+int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes)
+{
+    if (model != MCL_ISING && model != MCL_BC) return MCL_EMODEL;
+    if (!valid_L(L)) return MCL_EL;
+    if (!dev_bytes) return MCL_EARG;
+    *dev_bytes = layout_of(L).total;
+    return MCL_OK;
+}
+
+int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* always, int32_t cap)
+{
+    if (model != MCL_ISING && model != MCL_BC) return MCL_EMODEL;
+    if (std::isnan(beta) || beta < 0.0) return MCL_EBETA;
+    if (!thr) return MCL_EARG;
+    if (model == MCL_ISING) {
+        if (cap < 2) return MCL_EBUFSZ;
+        ising_thresholds(beta, thr[0], thr[1]);
+        return MCL_OK;
+    }
+    if (std::isnan(D)) return MCL_ED;
+    if (cap < 54 || !always) return cap < 54 ? MCL_EBUFSZ : MCL_EARG;
+    mcl::BCTable tb;
+    bc_table(beta, D, tb);
+    for (int i = 0; i < 54; ++i) {
+        thr[i] = tb.thr[i];
+        always[i] = (uint8_t)tb.always[i];
+    }
+    return MCL_OK;
+}
+
+int mcl_rset(int corr_mode, int64_t L, int64_t t, int32_t* r, int32_t cap, int32_t* n_needed)
+{
+    if (corr_mode != MCL_CORR_FULL && corr_mode != MCL_CORR_PROTOCOL) return MCL_EARG;
+    if (L < 2 || t < 0) return MCL_EARG;
+    if (corr_mode == MCL_CORR_PROTOCOL && !is_pow2(L)) return MCL_EL;
+    const std::vector<int32_t> d = distances(corr_mode, L, t, nullptr);
+    if (n_needed) *n_needed = (int32_t)d.size();
+    if ((int64_t)d.size() > cap || !r) return MCL_EBUFSZ;
+    std::memcpy(r, d.data(), d.size() * sizeof(int32_t));
+    return (int)d.size();
+}
+
+int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int init_state, void* dev_mem,
+                 int64_t dev_bytes, void* hip_stream)
+{
+    if (!out || !dev_mem) return MCL_EARG;
+    *out = nullptr;
+    if (model != MCL_ISING && model != MCL_BC) return MCL_EMODEL;
+    if (!valid_L(L)) return MCL_EL;
+    if (init_state < MCL_INIT_RANDOM || init_state > MCL_INIT_ZERO) return MCL_EINIT;
+    if (init_state == MCL_INIT_ZERO && model == MCL_ISING) return MCL_EINIT;
+    const Layout lay = layout_of(L);
+    if (dev_bytes < lay.total) return MCL_ENOMEM;
+    if (((uintptr_t)dev_mem & 255) != 0) return MCL_EARG;
+    mcl_lattice* h = new (std::nothrow) mcl_lattice;
+    if (!h) return MCL_EARG;
+    char* base = (char*)dev_mem;
+    h->model = model;
+    h->L = L;
+    h->seed = seed;
+    h->t = 0;
+    h->g.L = L;
+    h->g.W = L / 16;
+    h->g.Q = L / 64;
+    h->g.plane0 = (uint32_t*)(base + lay.planes);
+    h->acc = (int64_t*)(base + lay.acc);
+    h->rdev = (int32_t*)(base + lay.rlist);
+    h->Cx = (int64_t*)(base + lay.cx);
+    h->Cy = (int64_t*)(base + lay.cy);
+    h->rcap = lay.rcap;
+    h->stream = (hipStream_t)hip_stream;
+    const hipError_t e = mcl::launch_init(h->g, model, init_state, seed, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e);
+    }
+    *out = h;
+    return MCL_OK;
+}
+
+int lattice_free(mcl_lattice* h)
+{
+    if (!h) return MCL_EARG;
+    delete h;
+    return MCL_OK;
+}
+
+int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, int64_t* t)
+{
+    if (!h) return MCL_EARG;
+    if (model) *model = h->model;
+    if (L) *L = h->L;
+    if (seed) *seed = h->seed;
+    if (t) *t = h->t;
+    return MCL_OK;
+}
+
+int sweep(mcl_lattice* h, int64_t n, double beta, double D)
+{
+    if (!h || n < 0) return MCL_EARG;
+    const int pc = check_params(h, beta, D);
+    if (pc) return pc;
+    if (h->t + n > (int64_t(1) << 32)) return MCL_ERANGE;
+    mcl::HalfSweepArgs a{};
+    a.seed = h->seed;
+    mcl::BCTable tb{};
+    if (h->model == MCL_ISING) {
+        ising_thresholds(beta, a.T4, a.T8);
+    } else {
+        bc_table(beta, D, tb);
+        a.bc = &tb;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        a.t = (uint32_t)(h->t + i);
+        for (int c = 0; c < 2; ++c) {
+            a.color = c;
+            const hipError_t e = h->model == MCL_ISING ? mcl::launch_ising_half(h->g, a, h->stream)
+                                                       : mcl::launch_bc_half(h->g, a, h->stream);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+    }
+    h->t += n;
+    return MCL_OK;
+}
+
+int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
+{
+    if (!h || !out) return MCL_EARG;
+    if (corr_mode != MCL_CORR_NONE && corr_mode != MCL_CORR_FULL && corr_mode != MCL_CORR_PROTOCOL) return MCL_EARG;
+    if (corr_mode == MCL_CORR_PROTOCOL && !is_pow2(h->L)) return MCL_EL;
+    std::vector<int32_t> r;
+    int32_t n_all = 0;
+    if (corr_mode != MCL_CORR_NONE) {
+        r = distances(corr_mode, h->L, h->t, &n_all);
+        out->n_r = (int32_t)r.size();
+        if ((int64_t)r.size() > out->r_cap) return MCL_EBUFSZ;
+        if (!out->r || !out->Cx || !out->Cy || !out->nsrc) return MCL_EARG;
+        if ((int64_t)r.size() > h->rcap) return MCL_EBUFSZ;
+    } else {
+        out->n_r = 0;
+    }
+    const int nr = (int)r.size();
+    MCL_HIP(mcl::launch_zero(h->acc, mcl::kAccSlots, h->stream));
+    if (nr > 0) {
+        MCL_HIP(hipMemcpyAsync(h->rdev, r.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+        MCL_HIP(mcl::launch_zero(h->Cx, nr, h->stream));
+        MCL_HIP(mcl::launch_zero(h->Cy, nr, h->stream));
+    }
+    MCL_HIP(mcl::launch_bmq(h->g, h->acc, h->stream));
+    if (nr > 0) {
+        MCL_HIP(mcl::launch_corr_all(h->g, h->rdev, n_all, h->Cx, h->Cy, h->stream));
+        MCL_HIP(mcl::launch_corr_sampled(h->g, h->rdev + n_all, nr - n_all, h->Cx + n_all, h->Cy + n_all,
+                                         h->stream));
+    }
+    int64_t acc[mcl::kAccSlots];
+    MCL_HIP(hipMemcpyAsync(acc, h->acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    if (nr > 0) {
+        MCL_HIP(hipMemcpyAsync(out->Cx, h->Cx, nr * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+        MCL_HIP(hipMemcpyAsync(out->Cy, h->Cy, nr * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+    }
+    MCL_HIP(hipStreamSynchronize(h->stream));
+    out->B = acc[0];
+    out->M = acc[1];
+    out->Q = acc[2] + acc[3];
+    out->counts[0] = acc[3];
+    out->counts[1] = acc[4];
+    out->counts[2] = acc[2];
+    out->invalid = acc[5];
+    out->t = h->t;
+    const int64_t all_src = h->L * h->L;
+    const int64_t sampled_src = (h->L / 16) * (h->L / 16);
+    for (int j = 0; j < nr; ++j) {
+        out->r[j] = r[j];
+        out->nsrc[j] = (j < n_all) ? all_src : sampled_src;
+    }
+    return MCL_OK;
+}
+
+int lattice_read_packed(mcl_lattice* h, void* host, int64_t bytes)
+{
+    if (!h || !host) return MCL_EARG;
+    const int64_t need = h->L * h->L / 2;
+    if (bytes < need) return MCL_EBUFSZ;
+    MCL_HIP(hipStreamSynchronize(h->stream));
+    MCL_HIP(hipMemcpyAsync(host, h->g.plane0, need, hipMemcpyDeviceToHost, h->stream));
+    MCL_HIP(hipStreamSynchronize(h->stream));
+    return MCL_OK;
+}
+
+int lattice_write_packed(mcl_lattice* h, const void* host, int64_t bytes, int64_t t)
+{
+    if (!h || !host) return MCL_EARG;
+    if (t < 0 || t > (int64_t(1) << 32)) return MCL_ERANGE;
+    const int64_t need = h->L * h->L / 2;
+    if (bytes < need) return MCL_EBUFSZ;
+    MCL_HIP(hipMemcpyAsync(h->g.plane0, host, need, hipMemcpyHostToDevice, h->stream));
+    MCL_HIP(hipStreamSynchronize(h->stream));
+    h->t = t;
+    return MCL_OK;
+}
+
+int lattice_read(mcl_lattice* h, int8_t* host_spins)
+{
+    if (!h || !host_spins) return MCL_EARG;
+    const int64_t L = h->L, W = h->g.W;
+    std::vector<uint32_t> buf((size_t)(2 * L * W));
+    const int rc = lattice_read_packed(h, buf.data(), (int64_t)buf.size() * 4);
+    if (rc) return rc;
+    for (int64_t y = 0; y < L; ++y)
+        for (int64_t x = 0; x < L; ++x) {
+            const int c = (int)((x + y) & 1);
+            const int64_t i = x >> 1;
+            host_spins[y * L + x] = cell_to_spin(buf[(size_t)(c * L * W + y * W + (i >> 3))], i);
+        }
+    return MCL_OK;
+}
+
+int lattice_read_window(mcl_lattice* h, int64_t x0, int64_t y0, int64_t w, int64_t hgt, int8_t* host_spins)
+{
+    if (!h || !host_spins) return MCL_EARG;
+    const int64_t L = h->L, W = h->g.W;
+    if (w <= 0 || hgt <= 0 || w > L || hgt > L || x0 < 0 || y0 < 0 || x0 >= L || y0 >= L) return MCL_ERANGE;
+    MCL_HIP(hipStreamSynchronize(h->stream));
+    std::vector<uint32_t> rows((size_t)(2 * W));
+    for (int64_t dy = 0; dy < hgt; ++dy) {
+        const int64_t y = (y0 + dy) % L;
+        for (int c = 0; c < 2; ++c)
+            MCL_HIP(hipMemcpyAsync(rows.data() + c * W, h->g.plane(c) + y * W, W * 4, hipMemcpyDeviceToHost,
+                                   h->stream));
+        MCL_HIP(hipStreamSynchronize(h->stream));
+        for (int64_t dx = 0; dx < w; ++dx) {
+            const int64_t x = (x0 + dx) % L;
+            const int c = (int)((x + y) & 1);
+            const int64_t i = x >> 1;
+            host_spins[dy * w + dx] = cell_to_spin(rows[(size_t)(c * W + (i >> 3))], i);
+        }
+    }
+    return MCL_OK;
+}
+
+int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t)
+{
+    if (!h || !host_spins) return MCL_EARG;
+    if (t < 0 || t > (int64_t(1) << 32)) return MCL_ERANGE;
+    const int64_t L = h->L, W = h->g.W;
+    std::vector<uint32_t> buf((size_t)(2 * L * W), 0u);
+    for (int64_t y = 0; y < L; ++y)
+        for (int64_t x = 0; x < L; ++x) {
+            const int s = host_spins[y * L + x];
+            const bool ok = (h->model == MCL_ISING) ? (s == 1 || s == -1) : (s >= -1 && s <= 1);
+            if (!ok) return MCL_ESPINS;
+            const int c = (int)((x + y) & 1);
+            const int64_t i = x >> 1;
+            buf[(size_t)(c * L * W + y * W + (i >> 3))] |= (uint32_t)(s + 1) << (4 * (i & 7));
+        }
+    return lattice_write_packed(h, buf.data(), (int64_t)buf.size() * 4, t);
+}
+
+int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
+{
+    if (count < 0 || (count > 0 && (!hs || !n || !beta || !D))) return MCL_EARG;
+    int64_t nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || n[i] < 0) return MCL_EARG;
+        const int pc = check_params(hs[i], beta[i], D[i]);
+        if (pc) return pc;
+        if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
+        nmax = std::max(nmax, n[i]);
+    }
+    for (int64_t s = 0; s < nmax; ++s)
+        for (int i = 0; i < count; ++i)
+            if (n[i] > s) {
+                const int rc = sweep(hs[i], 1, beta[i], D[i]);
+                if (rc) return rc;
+            }
+    return MCL_OK;
+}
+
+}  // extern "C"

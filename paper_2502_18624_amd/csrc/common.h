@@ -1,0 +1,92 @@
+// Device-side building blocks shared by the library's kernels (gfx950).
+//
+// Storage layout of one lattice (L a multiple of 64):
+//   two colour planes P_0, P_1 (checkerboard decomposition, section 3.1);
+//   plane c holds the sites of colour c = (x + y) & 1, row-major, L rows of
+//   L/2 cells, the cell of site (x, y) at in-plane index i = x >> 1;
+//   4 bits per cell, 8 cells per 32-bit word (cell i in bits 4(i&7)..+3 of
+//   word i >> 3), so a row is L/16 words = L/64 16-byte vectors;
+//   cell value n = s + 1 (Ising uses 0 and 2, Blume-Capel 0, 1, 2), so the
+//   sum of four neighbour cells is at most 8 and fits its nibble (the
+//   multi-spin coding of section 3.2).
+//   Plane P_1 follows P_0 directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcl {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// products and xors, key advanced by the Weyl constants between rounds.
+// The products are written as 64-bit multiplies so that each maps to one
+// v_mad_u64_u32; the key stays wave-uniform (SGPRs) when the caller's is.
+struct Philox4 {
+    uint32_t v0, v1, v2, v3;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+// ({hi, lo} >> sh)[31:0], sh in 0..31 (one v_alignbit_b32).
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Number of set bits.
+__device__ __forceinline__ uint32_t popc(uint32_t v) { return __builtin_popcount(v); }
+
+// Sum over the 8 cell pairs of two words of s * s', s = n - 1 for n in
+// {0, 1, 2}: a product is nonzero iff neither cell is 1 (bit 0 clear in
+// both) and is +1 iff their bit 1 agrees.
+__device__ __forceinline__ int pair_products(uint32_t a, uint32_t b)
+{
+    const uint32_t nz = ~(a | b) & 0x11111111u;
+    const uint32_t diff = ((a ^ b) >> 1) & nz;
+    return (int)popc(nz) - 2 * (int)popc(diff);
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Blume-Capel acceptance table entry: threshold and "always accept" flag
+// (dE <= 0), indexed ((n * 2) + b) * 9 + neighbour-cell-sum, n = s + 1.
+struct BCTable {
+    uint32_t thr[54];
+    uint32_t always[54];
+};
+
+}  // namespace mcl

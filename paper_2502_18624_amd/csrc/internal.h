@@ -1,0 +1,48 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mcl {
+
+// Geometry of one lattice in device memory (layout described in common.h).
+struct Geom {
+    int64_t L;          // linear size, multiple of 64
+    int64_t W;          // 32-bit words per plane row = L / 16
+    int64_t Q;          // 16-byte vectors per plane row = L / 64
+    uint32_t* plane0;   // colour 0 cells; colour 1 follows at plane0 + L * W
+    uint32_t* plane(int c) const { return plane0 + (c ? L * W : 0); }
+    int64_t plane_words() const { return L * W; }
+};
+
+// a1: write the initial state into both planes.
+hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, hipStream_t s);
+
+// a3 / a4: one colour of one sweep.
+struct HalfSweepArgs {
+    int color;
+    uint32_t t;
+    uint64_t seed;
+    uint32_t T4, T8;        // Ising thresholds (e^{-4 beta}, e^{-8 beta})
+    const BCTable* bc;      // Blume-Capel table (host copy, passed by value)
+};
+hipError_t launch_ising_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
+hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
+
+// a6 / a7: measurement kernels accumulating into int64 device scratch.
+// acc layout: [0] B, [1] M (from +1 count minus -1 count), [2] #(+1),
+// [3] #(-1), [4] #(0), [5] invalid cells, [6..14] reserved.
+constexpr int kAccSlots = 16;
+hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s);
+hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s);
+// Correlations from every source at distances r[0..nr).
+hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
+                           hipStream_t s);
+// Correlations from the sampled sources x = y = 0 (mod 16) at r[0..nr).
+hipError_t launch_corr_sampled(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
+                               hipStream_t s);
+
+}  // namespace mcl

@@ -1,0 +1,155 @@
+"""Python face of the library: a :class:`Lattice` owns a torch device buffer
+and a library handle; every call marshals arguments into the C ABI of
+``include/mcl.h``.  PyTorch provides device memory and the stream only."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_DOWN, INIT_RANDOM, INIT_UP,  # noqa: F401
+                   INIT_ZERO, ISING, MeasureOut, check, lib)
+
+_ALIGN = 256
+
+
+def query_bytes(model: int, L: int) -> int:
+    out = ctypes.c_int64()
+    check(lib().mcl_query_bytes(model, L, ctypes.byref(out)), "mcl_query_bytes")
+    return out.value
+
+
+def rset(mode: int, L: int, t: int = 0) -> np.ndarray:
+    need = ctypes.c_int32()
+    rc = lib().mcl_rset(mode, L, t, None, 0, ctypes.byref(need))
+    if rc not in (0, -10):
+        check(rc, "mcl_rset")
+    buf = np.zeros(max(need.value, 1), dtype=np.int32)
+    n = check(lib().mcl_rset(mode, L, t, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             len(buf), ctypes.byref(need)), "mcl_rset")
+    return buf[:n].copy()
+
+
+def thresholds(model: int, beta: float, D: float = 0.0):
+    """Ising: (T4, T8).  Blume-Capel: (thr[54], always[54])."""
+    thr = np.zeros(54, dtype=np.uint32)
+    alw = np.zeros(54, dtype=np.uint8)
+    check(lib().mcl_thresholds(model, float(beta), float(D),
+                               thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               alw.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 54), "mcl_thresholds")
+    if model == ISING:
+        return int(thr[0]), int(thr[1])
+    return thr, alw.astype(bool)
+
+
+class Lattice:
+    """One L x L lattice resident in HBM (two 4-bit colour planes)."""
+
+    def __init__(self, model: int, L: int, seed: int, init: int = INIT_RANDOM, device="cuda",
+                 stream=None, mem=None):
+        import torch
+
+        self.model, self.L, self.seed = int(model), int(L), int(seed)
+        self.nbytes = query_bytes(self.model, self.L)
+        if mem is None:
+            mem = torch.empty(self.nbytes + _ALIGN, dtype=torch.uint8, device=device)
+        self.mem = mem
+        base = mem.data_ptr()
+        self.ptr = (base + _ALIGN - 1) // _ALIGN * _ALIGN
+        if self.ptr + self.nbytes > base + mem.numel():
+            raise ValueError("device buffer too small for L=%d" % L)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(mem.device)
+        self._h = ctypes.c_void_p()
+        check(lib().lattice_init(ctypes.byref(self._h), self.model, self.L, self.seed, int(init),
+                                 ctypes.c_void_p(self.ptr), self.nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream)), "lattice_init")
+
+    # -- state -----------------------------------------------------------
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().lattice_info(self._h, None, None, None, ctypes.byref(t)), "lattice_info")
+        return t.value
+
+    # -- the method ------------------------------------------------------
+    def sweep(self, n: int, beta: float, D: float = 0.0) -> None:
+        check(lib().sweep(self._h, int(n), float(beta), float(D)), "sweep")
+
+    def measure(self, corr: int = CORR_NONE) -> dict:
+        out = MeasureOut()
+        cap = 0
+        if corr != CORR_NONE:
+            cap = len(rset(corr, self.L, self.t))
+        r = np.zeros(max(cap, 1), dtype=np.int32)
+        cx = np.zeros(max(cap, 1), dtype=np.int64)
+        cy = np.zeros(max(cap, 1), dtype=np.int64)
+        ns = np.zeros(max(cap, 1), dtype=np.int64)
+        out.r = r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        out.Cx = cx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        out.Cy = cy.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        out.nsrc = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        out.r_cap = cap
+        check(lib().measure(self._h, int(corr), ctypes.byref(out)), "measure")
+        n = out.n_r
+        return {"B": out.B, "M": out.M, "Q": out.Q, "t": out.t, "counts": list(out.counts),
+                "invalid": out.invalid, "r": r[:n].copy(), "Cx": cx[:n].copy(), "Cy": cy[:n].copy(),
+                "nsrc": ns[:n].copy()}
+
+    # -- host copies (parity checks, checkpoints) -------------------------
+    def read(self) -> np.ndarray:
+        s = np.empty((self.L, self.L), dtype=np.int8)
+        check(lib().lattice_read(self._h, s.ctypes.data_as(ctypes.c_void_p)), "lattice_read")
+        return s
+
+    def read_window(self, x0: int, y0: int, w: int, h: int) -> np.ndarray:
+        s = np.empty((h, w), dtype=np.int8)
+        check(lib().lattice_read_window(self._h, x0, y0, w, h, s.ctypes.data_as(ctypes.c_void_p)),
+              "lattice_read_window")
+        return s
+
+    def write(self, spins: np.ndarray, t: int) -> None:
+        s = np.ascontiguousarray(spins, dtype=np.int8)
+        if s.shape != (self.L, self.L):
+            raise ValueError("expected shape (%d, %d)" % (self.L, self.L))
+        check(lib().lattice_write(self._h, s.ctypes.data_as(ctypes.c_void_p), int(t)), "lattice_write")
+
+    def read_packed(self) -> np.ndarray:
+        buf = np.empty(self.L * self.L // 2, dtype=np.uint8)
+        check(lib().lattice_read_packed(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+              "lattice_read_packed")
+        return buf
+
+    def write_packed(self, buf: np.ndarray, t: int) -> None:
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lib().lattice_write_packed(self._h, b.ctypes.data_as(ctypes.c_void_p), b.nbytes, int(t)),
+              "lattice_write_packed")
+
+    def free(self) -> None:
+        if self._h:
+            lib().lattice_free(self._h)
+            self._h = ctypes.c_void_p()
+            self.mem = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def group_sweep(lattices, n, beta, D=None) -> None:
+    """Batched path: advance each lattice i by n[i] sweeps at (beta[i], D[i])."""
+    k = len(lattices)
+    n = list(n) if np.ndim(n) else [int(n)] * k
+    beta = list(beta) if np.ndim(beta) else [float(beta)] * k
+    D = [0.0] * k if D is None else (list(D) if np.ndim(D) else [float(D)] * k)
+    hs = (ctypes.c_void_p * k)(*[l.handle.value for l in lattices])
+    nn = (ctypes.c_int64 * k)(*[int(v) for v in n])
+    bb = (ctypes.c_double * k)(*[float(v) for v in beta])
+    dd = (ctypes.c_double * k)(*[float(v) for v in D])
+    check(lib().group_sweep(hs, k, nn, bb, dd), "group_sweep")

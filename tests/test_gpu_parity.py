@@ -1,0 +1,172 @@
+"""GPU vs oracle, bit-exact: lattices after n sweeps, and the integer
+measurement sums, through the C ABI on the same seeded inputs.  Sizes span
+one to many 16-byte columns per row (L = 64 is a single column), non-power-
+of-two L, and every temperature regime including beta = infinity."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = math.log(1 + math.sqrt(2)) / 2
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_18624_amd as m
+    m.lib()
+    return m
+
+
+def _oracle_run(model, L, seed, init, n, beta, D, t0=0, start=None):
+    s = oracle.init(model, L, seed, init) if start is None else start.copy()
+    if n:
+        oracle.sweep(s, model, seed, t0, n, beta, D)
+    return s
+
+
+@pytest.mark.parametrize("model,init", [(0, 0), (0, 1), (0, 2), (1, 0), (1, 1), (1, 2), (1, 3)])
+@pytest.mark.parametrize("L", [64, 192, 256])
+def test_init_parity(mcl, model, init, L):
+    print("init parity", model, init, L, flush=True)
+    lat = mcl.Lattice(model, L, 1001 + L, init)
+    assert np.array_equal(lat.read(), oracle.init(model, L, 1001 + L, init))
+
+
+ISING_CASES = [
+    (64, 1, 1, BETA_C / 0.9), (64, 2, 17, BETA_C), (128, 3, 3, BETA_C / 0.5), (256, 1001, 17, BETA_C / 0.9),
+    (256, 5, 2, INF), (192, 6, 5, BETA_C / 1.5), (512, 7, 3, BETA_C), (1024, 8, 2, BETA_C / 0.9),
+    (320, 9, 4, 0.0),
+]
+
+
+@pytest.mark.parametrize("L,seed,n,beta", ISING_CASES)
+def test_ising_sweep_parity(mcl, L, seed, n, beta):
+    print("ising sweep parity", L, seed, n, beta, flush=True)
+    lat = mcl.Lattice(mcl.ISING, L, seed)
+    lat.sweep(n, beta)
+    got = lat.read()
+    want = _oracle_run(0, L, seed, 0, n, beta, 0.0)
+    assert lat.t == n
+    assert np.array_equal(got, want), "mismatch at %d cells" % int((got != want).sum())
+
+
+BC_CASES = [
+    (64, 11, 1, 1 / 1.4, 1.0), (64, 12, 17, 0.6, 0.0), (128, 13, 3, 1.0, 0.5), (256, 1003, 5, 1 / 1.4, 1.0),
+    (256, 14, 3, INF, 1.0), (192, 15, 4, 0.5, -3.0), (512, 16, 2, 0.8, 0.5), (1024, 17, 2, 1 / 1.4, 1.0),
+    (128, 18, 3, 0.0, 2.0),
+]
+
+
+@pytest.mark.parametrize("L,seed,n,beta,D", BC_CASES)
+def test_bc_sweep_parity(mcl, L, seed, n, beta, D):
+    print("bc sweep parity", L, seed, n, beta, D, flush=True)
+    lat = mcl.Lattice(mcl.BC, L, seed)
+    lat.sweep(n, beta, D)
+    got = lat.read()
+    want = _oracle_run(1, L, seed, 0, n, beta, D)
+    assert np.array_equal(got, want), "mismatch at %d cells" % int((got != want).sum())
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_split_calls_and_restart(mcl, model):
+    """n sweeps in pieces, and a restore from a host copy at t0, equal the
+    oracle's uninterrupted run."""
+    print("split/restart", model, flush=True)
+    L, seed, beta, D = 128, 77, BETA_C / 0.9, 0.5
+    a = mcl.Lattice(model, L, seed)
+    for n in (3, 1, 13):
+        a.sweep(n, beta, D)
+    want = _oracle_run(model, L, seed, 0, 17, beta, D)
+    assert np.array_equal(a.read(), want)
+    # checkpoint at t = 17, restore into a fresh handle, continue
+    snap, t = a.read(), a.t
+    b = mcl.Lattice(model, L, seed)
+    b.write(snap, t)
+    b.sweep(5, beta, D)
+    a.sweep(5, beta, D)
+    assert np.array_equal(a.read(), b.read())
+    assert np.array_equal(b.read(), _oracle_run(model, L, seed, 0, 5, beta, D, t0=17, start=snap))
+    # packed checkpoint
+    c = mcl.Lattice(model, L, seed)
+    c.write_packed(a.read_packed(), a.t)
+    c.sweep(2, beta, D)
+    a.sweep(2, beta, D)
+    assert np.array_equal(a.read(), c.read())
+
+
+def test_write_arbitrary_state(mcl):
+    rng = np.random.default_rng(5)
+    for model, vals in ((0, [-1, 1]), (1, [-1, 0, 1])):
+        s = rng.choice(vals, size=(128, 128)).astype(np.int8)
+        lat = mcl.Lattice(model, 128, 3)
+        lat.write(s, 40)
+        assert np.array_equal(lat.read(), s)
+        lat.sweep(3, 0.7, 0.3)
+        assert np.array_equal(lat.read(), _oracle_run(model, 128, 3, 0, 3, 0.7, 0.3, t0=40, start=s))
+    with pytest.raises(mcl.MclError):
+        mcl.Lattice(0, 64, 1).write(np.zeros((64, 64), dtype=np.int8), 0)   # 0 is not an Ising spin
+
+
+def _check_measure(mcl, lat, mode):
+    s = lat.read()
+    m = lat.measure(mode)
+    om = oracle.measure(s)
+    assert (m["B"], m["M"], m["Q"], m["counts"], m["invalid"]) == (om["B"], om["M"], om["Q"], om["counts"], 0)
+    if mode != mcl.CORR_NONE:
+        r = oracle.rset(mode, lat.L, lat.t)
+        assert np.array_equal(m["r"], r)
+        Cx, Cy, ns = oracle.corr(s, mode, r)
+        assert np.array_equal(m["nsrc"], ns)
+        assert np.array_equal(m["Cx"], Cx), np.nonzero(m["Cx"] != Cx)
+        assert np.array_equal(m["Cy"], Cy), np.nonzero(m["Cy"] != Cy)
+
+
+@pytest.mark.parametrize("model,L,n", [(0, 64, 3), (0, 256, 8), (1, 128, 4), (1, 192, 2), (0, 320, 1)])
+def test_measure_full_parity(mcl, model, L, n):
+    print("measure full", model, L, n, flush=True)
+    lat = mcl.Lattice(model, L, 4242)
+    lat.sweep(n, BETA_C / 0.9, 1.0)
+    _check_measure(mcl, lat, mcl.CORR_FULL)
+
+
+@pytest.mark.parametrize("model,L,n", [(0, 64, 1), (0, 256, 16), (1, 512, 4), (0, 1024, 8), (1, 2048, 2)])
+def test_measure_protocol_parity(mcl, model, L, n):
+    print("measure protocol", model, L, n, flush=True)
+    lat = mcl.Lattice(model, L, 99)
+    lat.sweep(n, BETA_C, 1.0)
+    _check_measure(mcl, lat, mcl.CORR_PROTOCOL)
+    _check_measure(mcl, lat, mcl.CORR_NONE)
+
+
+def test_measure_structured_states(mcl):
+    """Closed forms through the device path: ordered states."""
+    L = 256
+    for model, init, val in ((0, 1, 1), (0, 2, -1), (1, 3, 0)):
+        lat = mcl.Lattice(model, L, 0, init)
+        m = lat.measure(mcl.CORR_PROTOCOL)
+        N = L * L
+        assert m["M"] == val * N and m["Q"] == abs(val) * N and m["B"] == 2 * N * val * val
+        assert np.array_equal(m["Cx"], abs(val) * m["nsrc"]) and np.array_equal(m["Cy"], abs(val) * m["nsrc"])
+
+
+def test_group_sweep_equals_plain(mcl):
+    rng = np.random.default_rng(3)
+    specs = []
+    for i in range(6):
+        model = i % 2
+        L = int(rng.choice([64, 128, 256]))
+        specs.append((model, L, 2000 + i, int(rng.integers(1, 6)), float(rng.uniform(0.5, 1.5)) * BETA_C,
+                      float(rng.choice([0.0, 0.5, 1.0]))))
+    lats = [mcl.Lattice(m, L, s) for (m, L, s, _, _, _) in specs]
+    mcl.group_sweep(lats, [sp[3] for sp in specs], [sp[4] for sp in specs], [sp[5] for sp in specs])
+    for lat, (m, L, s, n, b, D) in zip(lats, specs):
+        assert lat.t == n
+        assert np.array_equal(lat.read(), _oracle_run(m, L, s, 0, n, b, D))
