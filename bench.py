@@ -21,7 +21,14 @@ if ROOT not in sys.path:
 
 BETA_C = math.log(1.0 + math.sqrt(2.0)) / 2.0
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit lane
+# instructions/s.  One Philox4x32-10 block needs 10 rounds x (2 wide
+# multiplies + 2 three-input xors) = 40 of them at the least on gfx950.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+PHILOX_OPS_PER_BLOCK = 40
+PHILOX_PEAK_GBLOCKS = VALU_LANE_OPS / PHILOX_OPS_PER_BLOCK / 1e9
 METRIC = "lattice updates/ns on 1 MI355X (Ising L=2^17); % HBM peak; batched vs plain"
+SWEEP_SOURCES = ["paper_2502_18624_amd/csrc/sweep.hip", "paper_2502_18624_amd/csrc/common.h"]
 
 
 def log(*a):
@@ -48,6 +55,44 @@ def cpu_baseline(budget_s=12.0):
     return {"value": round(L * L * done / (el * 1e9), 5), "unit": "updates/ns", "cores": cores, "kind": "oracle",
             "sample": "Ising L=2^13 at T_c from a random start, %d sweeps (%.1f s), rows of one colour split over "
                       "%d OpenMP threads" % (done, el, cores)}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(L):
+    """HBM bytes per half-sweep launch from the committed PMC summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_ising_half_sweep_L%d.json" % L)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def attainable_copy():
+    """Copy-kernel bandwidth from the calibration program (GB/s), or None."""
+    import re
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2502_18624_amd", "mcl_calibrate")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe, "copy"], capture_output=True, text=True, timeout=60).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    vals = [float(v) for v in re.findall(r"copy .*?([0-9.]+) GB/s", out)]
+    return max(vals) if vals else None
 
 
 def run(args):
@@ -91,6 +136,7 @@ def run(args):
             ev.append((a, b, m - done))
             done = m
         if m in marks and (not measures or measures[-1]["t"] != m):
+            torch.cuda.synchronize()        # the measurement's time excludes the sweeps before it
             tm = time.perf_counter()
             out = lat.measure(mcl.CORR_PROTOCOL)
             t_meas += time.perf_counter() - tm
@@ -104,8 +150,11 @@ def run(args):
     assert n_sweeps == args.steps and lat.t == args.steps
     updates = float(L) * L * args.steps
     half_ms = sweep_ms / (2 * n_sweeps)
+    half_updates = L * L / 2.0
     half_bytes = 3.0 * L * L / 4.0                 # read P_c, read P_{1-c}, write P_c (4-bit cells)
-    achieved = half_bytes / (half_ms * 1e-3) / 1e9
+    hbm_gbs = half_bytes / (half_ms * 1e-3) / 1e9
+    blocks_gps = half_updates / 4.0 / (half_ms * 1e-3) / 1e9   # one 32-bit draw per update
+    traffic = measured_traffic(L)
     res = {
         "metric": METRIC,
         "value": round(updates / (wall * 1e9), 2),
@@ -117,18 +166,23 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u4 (4-bit spin cells, u32 Philox draws)",
+        "dtype": "u4 cells, u32 Philox draws (integer path)",
         "data": "synthetic (seeded Philox4x32-10 random start)",
         "config": {"workload": "Ising quench, L=2^17, T=T_c, random +-1 start, %d sweeps, protocol C(r,t) and "
                                "B/M at t=2^k, one lattice per launch" % args.steps,
                    "L": L, "seed": seed, "beta": beta, "measure_times": marks},
         "sweep_only_updates_per_ns": round(updates / (sweep_ms * 1e6), 2),
         "measure_share": round(t_meas / wall, 4),
-        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+        "hbm_achieved_GBs": round(hbm_gbs, 1),
+        "hbm_attainable_copy_GBs": attainable_copy(),
+        "roofline": {"bound": "alu", "achieved": round(blocks_gps, 1), "peak": round(PHILOX_PEAK_GBLOCKS, 1),
+                     "unit": "Gblocks/s", "frac": round(blocks_gps / PHILOX_PEAK_GBLOCKS, 4),
+                     "traffic": traffic,
                      "kernel": "half_sweep_kernel<Ising>", "avg_launch_ms": round(half_ms, 4),
-                     "bytes_per_launch": half_bytes},
+                     "work_per_launch": "%d Philox4x32-10 blocks (one u32 draw per update), %d bytes" % (
+                         int(half_updates / 4), int(half_bytes)),
+                     "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)},
         "paper_context": {"updates_per_ns": 1797, "hardware": "1x GB200, 1-bit cells with LUT random bits",
                           "note": "context only"},
         "measures": measures,

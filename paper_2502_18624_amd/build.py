@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcl.so")
-SOURCES = ["api.hip", "sweep.hip", "measure.hip", "batch.hip"]
+SOURCES = ["api.hip", "sweep.hip", "measure.hip", "batch.hip"]  # calibrate.hip is a separate program
 
 # Packed-FP32 instructions are switched off for all device code; the
 # library has no floating point on the device, but the flag keeps the
@@ -39,5 +39,20 @@ def build_library(extra_flags=None, out=LIB, verbose=False) -> str:
     return out
 
 
+CALIBRATE = os.path.join(HERE, "mcl_calibrate")
+
+
+def build_calibrate(out=CALIBRATE) -> str:
+    """Standalone calibration program (copy / Philox / VALU rates)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "calibrate.hip")]
+    res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build_library(verbose=True))
+    print(build_calibrate())

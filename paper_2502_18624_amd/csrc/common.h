@@ -22,10 +22,18 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// a ^ b ^ c in one VALU instruction (v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
 // products and xors, key advanced by the Weyl constants between rounds.
-// The products are written as 64-bit multiplies so that each maps to one
-// v_mad_u64_u32; the key stays wave-uniform (SGPRs) when the caller's is.
+// Each product is one v_mad_u64_u32 and each pair of xors one v_bitop3_b32.
+// The first two rounds use plain xors: when the caller's counter words 1..3
+// and key are wave-uniform (the sweep index, the stream and a zero high
+// word), the compiler moves half of those rounds' work to the scalar unit.
 struct Philox4 {
     uint32_t v0, v1, v2, v3;
 };
@@ -37,8 +45,14 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (r < 2) {
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+            n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        }
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -47,6 +61,25 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
         k1 += kPhiloxW1;
     }
     return Philox4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t philox_word(const Philox4& p, int i)
+{
+    return i == 0 ? p.v0 : i == 1 ? p.v1 : i == 2 ? p.v2 : p.v3;
+}
+
+// acc * 2 + [u < T]: the comparison's carry goes straight into an
+// add-with-carry (two VALU instructions; T must live in an SGPR).  Left to
+// itself the compiler builds such masks with compare, select and or.
+__device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32_t T)
+{
+    uint32_t r;
+    asm("v_cmp_gt_u32_e32 vcc, %2, %1\n\t"
+        "v_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+        : "=v"(r)
+        : "v"(u), "s"(T), "v"(acc)
+        : "vcc");
+    return r;
 }
 
 // ({hi, lo} >> sh)[31:0], sh in 0..31 (one v_alignbit_b32).

@@ -100,46 +100,51 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 
 constexpr int kRChunk = 16;
 
-// Word of cells i + m .. i + m + 7 of row `row` (W words, periodic) where
-// i = 8 * wd.
-__device__ __forceinline__ uint32_t shifted_word(const uint32_t* __restrict__ row, int64_t W, int64_t wd, int64_t m)
+__device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n ? v - n : v; }
+
+// Word of cells i + m .. i + m + 7 (periodic in the row of W words), where
+// cell i is cell 0 of word wd; m < 8 W.
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t* __restrict__ row, uint32_t W, uint32_t wd, uint32_t m)
 {
-    const int64_t base = wd + (m >> 3);
-    const int64_t w0 = base % W;
-    const int64_t w1 = (base + 1) % W;
-    return funnel(row[w1], row[w0], (uint32_t)(4 * (m & 7)));
+    const uint32_t w0 = wrap(wd + (m >> 3), W);
+    const uint32_t w1 = wrap(w0 + 1, W);
+    return funnel(row[w1], row[w0], 4 * (m & 7));
 }
 
-__global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restrict__ planes, int64_t L, int64_t rows,
+// Every source: one thread per (plane, band of rows, 16-byte column), a
+// chunk of up to kRChunk distances per grid row.
+__global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restrict__ planes, uint32_t L, uint32_t rows,
                                                        const int32_t* __restrict__ rlist, int nr,
                                                        int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
 {
-    const int64_t Q = L >> 6, W = L >> 4;
+    const uint32_t Q = L >> 6, W = L >> 4;
     const int j0 = blockIdx.y * kRChunk;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q = g % Q;
-    const int64_t rest = g / Q;
-    const int64_t nbands = L / rows;
-    const int c = (int)(rest / nbands);
-    const int64_t band = rest - (int64_t)c * nbands;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t q = g % Q;
+    const uint32_t rest = g / Q;
+    const uint32_t nbands = L / rows;
+    const uint32_t c = rest / nbands;
+    const uint32_t band = rest - c * nbands;
+    const size_t plane_words = (size_t)L * W;
     int cx[kRChunk], cy[kRChunk];
 #pragma unroll
     for (int j = 0; j < kRChunk; ++j) cx[j] = cy[j] = 0;
     if (c < 2) {
-        const uint32_t* own = planes + (c ? L * W : 0);
-        for (int64_t rr = 0; rr < rows; ++rr) {
-            const int64_t y = band * rows + rr;
-            const uint4 v = reinterpret_cast<const uint4*>(own)[y * Q + q];
+        const uint32_t* own = planes + (c ? plane_words : 0);
+        for (uint32_t rr = 0; rr < rows; ++rr) {
+            const uint32_t y = band * rows + rr;
+            const uint4 v = reinterpret_cast<const uint4*>(own)[(size_t)y * Q + q];
+            const uint32_t par = (y + c) & 1u;
 #pragma unroll
             for (int j = 0; j < kRChunk; ++j) {
                 if (j0 + j < nr) {
-                    const int64_t r = rlist[j0 + j];
-                    const int pc = c ^ (int)(r & 1);
-                    const uint32_t* pl = planes + (pc ? L * W : 0);
-                    const int64_t yr = (y + r) % L;
-                    const uint4 py = reinterpret_cast<const uint4*>(pl)[yr * Q + q];
-                    const int64_t m = (r & 1) ? ((r - 1) >> 1) + ((y + c) & 1) : (r >> 1);
-                    const uint32_t* prow = pl + y * W;
+                    const uint32_t r = (uint32_t)rlist[j0 + j];
+                    const uint32_t pc = c ^ (r & 1u);
+                    const uint32_t* pl = planes + (pc ? plane_words : 0);
+                    const uint32_t yr = wrap(y + r, L);
+                    const uint4 py = reinterpret_cast<const uint4*>(pl)[(size_t)yr * Q + q];
+                    const uint32_t m = (r & 1u) ? ((r - 1) >> 1) + par : (r >> 1);
+                    const uint32_t* prow = pl + (size_t)y * W;
                     int sx = 0, sy = 0;
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
@@ -164,33 +169,42 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
     }
 }
 
-__global__ __launch_bounds__(256) void corr_sampled_kernel(const uint32_t* __restrict__ planes, int64_t L,
-                                                           int64_t brows, const int32_t* __restrict__ rlist, int nr,
+// Sampled sources (x = y = 0 mod 16): cell 0 of word a of plane 0, row 16 b.
+// Partners: along x (16 a + r, 16 b) is cell (8 a + r / 2) mod (L / 2) of
+// row 16 b in plane r & 1; along y (16 a, 16 b + r) is cell 0 of word a of
+// row 16 b + r in plane r & 1.  Block order puts the distance chunks of one
+// band of source rows next to each other so their partner rows are shared
+// in cache.
+__global__ __launch_bounds__(256) void corr_sampled_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                           uint32_t brows, uint32_t ablocks, uint32_t nchunks,
+                                                           const int32_t* __restrict__ rlist, int nr,
                                                            int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
 {
-    const int64_t W = L >> 4;        // also the number of source columns (L / 16)
-    const int64_t nb = L >> 4;       // number of source rows
-    const int j0 = blockIdx.y * kRChunk;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t a = g % W;
-    const int64_t band = g / W;
+    const uint32_t W = L >> 4;       // words per row = number of source columns
+    const uint32_t nb = L >> 4;      // number of source rows
+    const uint32_t half = L >> 1;
+    const size_t plane_words = (size_t)L * W;
+    const uint32_t ab = blockIdx.x % ablocks;
+    const uint32_t chunk = (blockIdx.x / ablocks) % nchunks;
+    const uint32_t band = blockIdx.x / (ablocks * nchunks);
+    const int j0 = (int)chunk * kRChunk;
+    const uint32_t a = ab * blockDim.x + threadIdx.x;
     int cx[kRChunk], cy[kRChunk];
 #pragma unroll
     for (int j = 0; j < kRChunk; ++j) cx[j] = cy[j] = 0;
-    if (band * brows < nb) {
-        for (int64_t bb = 0; bb < brows; ++bb) {
-            const int64_t b = band * brows + bb;
-            const int64_t y = 16 * b;
-            const int src = (int)(planes[y * W + a] & 0xFu) - 1;
+    if (a < W && band * brows < nb) {
+        for (uint32_t bb = 0; bb < brows; ++bb) {
+            const uint32_t y = 16u * (band * brows + bb);
+            const int src = (int)(planes[(size_t)y * W + a] & 0xFu) - 1;
 #pragma unroll
             for (int j = 0; j < kRChunk; ++j) {
                 if (j0 + j < nr) {
-                    const int64_t r = rlist[j0 + j];
-                    const uint32_t* pl = planes + ((r & 1) ? L * W : 0);
-                    const int64_t i = (8 * a + (r >> 1)) % (L >> 1);
-                    const int px = (int)((pl[y * W + (i >> 3)] >> (4 * (i & 7))) & 0xFu) - 1;
-                    const int64_t yr = (y + r) % L;
-                    const int py = (int)(pl[yr * W + a] & 0xFu) - 1;
+                    const uint32_t r = (uint32_t)rlist[j0 + j];
+                    const uint32_t* pl = planes + ((r & 1u) ? plane_words : 0);
+                    const uint32_t i = wrap(8u * a + (r >> 1), half);
+                    const int px = (int)((pl[(size_t)y * W + (i >> 3)] >> (4 * (i & 7))) & 0xFu) - 1;
+                    const uint32_t yr = wrap(y + r, L);
+                    const int py = (int)(pl[(size_t)yr * W + a] & 0xFu) - 1;
                     cx[j] += src * px;
                     cy[j] += src * py;
                 }
@@ -240,7 +254,7 @@ hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t*
     const int64_t threads = 2 * g.Q * (g.L / rows);
     const uint32_t chunks = (uint32_t)((nr + kRChunk - 1) / kRChunk);
     hipLaunchKernelGGL(corr_all_kernel, dim3((uint32_t)((threads + 255) / 256), chunks), dim3(256), 0, s, g.plane0,
-                       g.L, rows, r_dev, nr, Cx, Cy);
+                       (uint32_t)g.L, (uint32_t)rows, r_dev, nr, Cx, Cy);
     return hipGetLastError();
 }
 
@@ -249,10 +263,11 @@ hipError_t launch_corr_sampled(const Geom& g, const int32_t* r_dev, int nr, int6
     if (nr <= 0) return hipSuccess;
     const int64_t nb = g.L / 16;
     const int64_t brows = pick_rows(nb, 8);
-    const int64_t threads = g.W * (nb / brows);
+    const uint32_t ablocks = (uint32_t)((g.W + 255) / 256);
     const uint32_t chunks = (uint32_t)((nr + kRChunk - 1) / kRChunk);
-    hipLaunchKernelGGL(corr_sampled_kernel, dim3((uint32_t)((threads + 255) / 256), chunks), dim3(256), 0, s,
-                       g.plane0, g.L, brows, r_dev, nr, Cx, Cy);
+    const int64_t blocks = (int64_t)ablocks * chunks * (nb / brows);
+    hipLaunchKernelGGL(corr_sampled_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, g.plane0, (uint32_t)g.L,
+                       (uint32_t)brows, ablocks, chunks, r_dev, nr, Cx, Cy);
     return hipGetLastError();
 }
 

@@ -18,6 +18,11 @@ namespace {
 __device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
 __device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 
+__device__ __forceinline__ uint32_t pick(const uint4& v, int d)
+{
+    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
+}
+
 // ---------------------------------------------------------------------------
 // a1: initial state.  One thread per 32-bit word (8 cells) of one plane.
 // ---------------------------------------------------------------------------
@@ -59,150 +64,254 @@ __global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes
     planes[g] = word;
 }
 
-// Accept-draw blocks for 8 consecutive in-plane cells starting at in-colour
-// site index k0 (a multiple of 8): Philox blocks k0/4 and k0/4 + 1.
-struct Draws8 {
-    uint32_t u[8];
-};
-
-__device__ __forceinline__ Draws8 accept_draws8(uint64_t blk, uint32_t t, uint32_t color, uint32_t k0,
-                                                uint32_t k1)
-{
-    const Philox4 a = philox4x32_10(lo32(blk), hi32(blk), t, color, k0, k1);
-    const Philox4 b = philox4x32_10(lo32(blk + 1), hi32(blk + 1), t, color, k0, k1);
-    Draws8 d;
-    d.u[0] = a.v0; d.u[1] = a.v1; d.u[2] = a.v2; d.u[3] = a.v3;
-    d.u[4] = b.v0; d.u[5] = b.v1; d.u[6] = b.v2; d.u[7] = b.v3;
-    return d;
-}
-
 // ---------------------------------------------------------------------------
-// a3: Ising word update (8 cells).  Cells hold n in {0, 2}, so n ^ src is 2
-// for a misaligned neighbour and 0 otherwise; the per-nibble sum halved is
-// the number of misaligned neighbours m.  The flip rule of section 3.2
-// (always if at most two neighbours are aligned, with e^{-4 beta} if three,
-// e^{-8 beta} if four) is: flip iff m + lvl >= 2, where
-// lvl = [u < T4] + [u < T8] (T8 <= T4, so u < T8 implies u < T4).
+// Acceptance bits of the 32 cells of one 16-byte vector.  Cell j (0..7) of
+// word d (0..3) is in-colour site kv + 8d + j; its accept draw is output
+// word j & 3 of Philox block (kv >> 2) + 2d + (j >> 2).  Returns, for each
+// threshold T, a 32-bit mask whose bit 4j + d is [u < T]: the "transposed"
+// order lets each mask be built with one carry-chain add per cell
+// (acc = acc + acc + carry) and lets word d read its cells' bits at nibble
+// bit 0 as (mask >> d) & 0x11111111.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t ising_word(uint32_t src, uint32_t up, uint32_t dn, uint32_t mid,
-                                               uint32_t hs, const Draws8& d, uint32_t T4, uint32_t T8)
+template <bool HI0>
+__device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t color, uint32_t k0, uint32_t k1,
+                                             uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
 {
-    uint32_t lvl = 0;
+    uint32_t a4 = 0, a8 = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-        lvl |= ((uint32_t)(d.u[j] < T4) + (uint32_t)(d.u[j] < T8)) << (4 * j);
-    const uint32_t m = ((up ^ src) + (dn ^ src) + (mid ^ src) + (hs ^ src)) >> 1;
-    const uint32_t f = (m + lvl + 0x66666666u) & 0x88888888u;
-    return src ^ (f >> 2);
-}
-
-// ---------------------------------------------------------------------------
-// a4: Blume-Capel word update (8 cells), table lookup per cell.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bc_word(uint32_t src, uint32_t up, uint32_t dn, uint32_t mid, uint32_t hs,
-                                            const Draws8& d, uint32_t pbits, const uint32_t* thr,
-                                            const uint32_t* always)
-{
-    const uint32_t sum = up + dn + mid + hs;
-    uint32_t out = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const uint32_t n = (src >> (4 * j)) & 0xFu;
-        const uint32_t hsum = (sum >> (4 * j)) & 0xFu;
-        const uint32_t b = (pbits >> j) & 1u;
-        uint32_t idx = (n * 2u + b) * 9u + hsum;
-        idx = idx < 53u ? idx : 53u;
-        const bool acc = always[idx] != 0u || d.u[j] < thr[idx];
-        uint32_t n2 = n + 1u + b;
-        n2 = n2 >= 3u ? n2 - 3u : n2;
-        const uint32_t nv = (n <= 2u && acc) ? n2 : n;
-        out |= nv << (4 * j);
-    }
-    return out;
-}
-
-__device__ __forceinline__ uint32_t pick(const uint4& v, int d)
-{
-    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
-}
-
-template <int MODEL>
-__global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
-                                                         int64_t L, int64_t rows, uint32_t color, uint32_t t,
-                                                         uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8,
-                                                         BCTable tbl)
-{
-    __shared__ uint32_t s_thr[54];
-    __shared__ uint32_t s_always[54];
-    if (MODEL == 1) {
-        if (threadIdx.x < 54) {
-            s_thr[threadIdx.x] = tbl.thr[threadIdx.x];
-            s_always[threadIdx.x] = tbl.always[threadIdx.x];
-        }
-        __syncthreads();
-    }
-    const int64_t Q = L >> 6;
-    const int64_t W = L >> 4;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q = g % Q;
-    const int64_t band = g / Q;
-    const int64_t y0 = band * rows;
-    if (y0 >= L) return;
-    const uint4* __restrict__ oth4 = reinterpret_cast<const uint4*>(oth);
-    uint4* __restrict__ own4 = reinterpret_cast<uint4*>(own);
-    const int64_t ym = (y0 == 0) ? L - 1 : y0 - 1;
-    uint4 up = oth4[ym * Q + q];
-    uint4 mid = oth4[y0 * Q + q];
-    const int64_t halfL = L >> 1;
-    for (int64_t r = 0; r < rows; ++r) {
-        const int64_t y = y0 + r;
-        const int64_t yd = (y + 1 == L) ? 0 : y + 1;
-        const uint4 dn = oth4[yd * Q + q];
-        const uint4 src = own4[y * Q + q];
-        const uint32_t odd = (uint32_t)((y + color) & 1);
-        const int64_t hw = odd ? ((4 * q + 4 == W) ? 0 : 4 * q + 4) : ((q == 0) ? W - 1 : 4 * q - 1);
-        const uint32_t halo = oth[y * W + hw];
-        // in-colour index of the first cell of this vector
-        const uint64_t kv = (uint64_t)(y * halfL + 32 * q);
-        uint32_t pbits = 0;
-        if (MODEL == 1) {
-            const uint64_t pb = kv >> 7;
-            const Philox4 p = philox4x32_10(lo32(pb), hi32(pb), t, 2u + color, k0, k1);
-            const uint32_t sel = (uint32_t)((kv >> 5) & 3);
-            pbits = sel == 0 ? p.v0 : sel == 1 ? p.v1 : sel == 2 ? p.v2 : p.v3;
-        }
-        uint32_t res[4];
+    for (int h = 1; h >= 0; --h) {
+        Philox4 P[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            const uint32_t w = pick(mid, d);
-            uint32_t hs;
-            if (odd) {
-                const uint32_t nxt = d < 3 ? pick(mid, d + 1) : halo;
-                hs = funnel(nxt, w, 4);
-            } else {
-                const uint32_t prv = d > 0 ? pick(mid, d - 1) : halo;
-                hs = funnel(w, prv, 28);
-            }
-            const Draws8 dr = accept_draws8((kv + 8 * d) >> 2, t, color, k0, k1);
-            if (MODEL == 0)
-                res[d] = ising_word(pick(src, d), pick(up, d), pick(dn, d), w, hs, dr, T4, T8);
-            else
-                res[d] = bc_word(pick(src, d), pick(up, d), pick(dn, d), w, hs, dr, pbits >> (8 * d), s_thr,
-                                 s_always);
+            const uint64_t b = blk0 + 2 * d + h;
+            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
         }
-        own4[y * Q + q] = make_uint4(res[0], res[1], res[2], res[3]);
-        up = mid;
-        mid = dn;
+#pragma unroll
+        for (int jj = 3; jj >= 0; --jj)
+#pragma unroll
+            for (int d = 3; d >= 0; --d) {
+                const uint32_t u = philox_word(P[d], jj);
+                a4 = shift_in_lt(a4, u, T4);
+                a8 = shift_in_lt(a8, u, T8);
+            }
+    }
+    m4 = a4;
+    m8 = a8;
+}
+
+// Horizontal neighbour word of word d of vector `mid`: cells i - 1 (even
+// row parity) or i + 1 (odd) of the other plane, with `halo` the adjacent
+// word outside the vector on that side.
+__device__ __forceinline__ uint32_t horizontal(const uint4& mid, int d, uint32_t halo, bool odd)
+{
+    const uint32_t w = pick(mid, d);
+    if (odd) return funnel(d < 3 ? pick(mid, d + 1) : halo, w, 4);
+    return funnel(w, d > 0 ? pick(mid, d - 1) : halo, 28);
+}
+
+// ---------------------------------------------------------------------------
+// a3: Ising vector update (32 cells).  Cells hold n in {0, 2}; n ^ src is 2
+// for a misaligned neighbour, so half the per-nibble sum of the four xors is
+// the number m of misaligned neighbours.  The flip rule of section 3.2
+// (always with at most two aligned neighbours, with probability e^{-4 beta}
+// with three, e^{-8 beta} with four) is: flip iff m + [u < T4] + [u < T8]
+// >= 2, since T8 <= T4.  Adding 6 moves that test to nibble bit 3.
+// ---------------------------------------------------------------------------
+template <bool HI0>
+__device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
+                                           uint32_t halo, bool odd, uint64_t blk0, uint32_t t, uint32_t color,
+                                           uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8)
+{
+    uint32_t m4, m8;
+    accept_masks<HI0>(blk0, t, color, k0, k1, T4, T8, m4, m8);
+    uint32_t res[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t s = pick(src, d);
+        const uint32_t hs = horizontal(mid, d, halo, odd);
+        const uint32_t m = ((pick(up, d) ^ s) + (pick(dn, d) ^ s) + (pick(mid, d) ^ s) + (hs ^ s)) >> 1;
+        const uint32_t lvl = ((m4 >> d) & 0x11111111u) + ((m8 >> d) & 0x11111111u);
+        const uint32_t f = (m + lvl + 0x66666666u) & 0x88888888u;
+        res[d] = s ^ (f >> 2);
+    }
+    return make_uint4(res[0], res[1], res[2], res[3]);
+}
+
+// ---------------------------------------------------------------------------
+// a4: Blume-Capel vector update (32 cells).  Per cell: the proposal
+// s' = ((n + 1 + b) mod 3) - 1 (n = s + 1, b the proposal bit), then a table
+// lookup on (n, b, sum of neighbour cells) gives the threshold and whether
+// dE <= 0; accept = always | (u < thr), as a 33-bit borrow
+// (0:u) - (always:thr).  Word-level: n + 1 + b and its reduction mod 3 are
+// nibble-parallel; the accept bits gate the new values in with a bit select.
+// ---------------------------------------------------------------------------
+// Spread the low 8 bits of x to bit 0 of the 8 nibbles.
+__device__ __forceinline__ uint32_t spread8(uint32_t x)
+{
+    x &= 0xFFu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
+
+template <bool HI0>
+__device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
+                                        uint32_t halo, bool odd, uint64_t blk0, uint32_t pbits, uint32_t t,
+                                        uint32_t color, uint32_t k0, uint32_t k1, const uint2* __restrict__ tab)
+{
+    uint32_t key[4], sum[4], nxt[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t s = pick(src, d);
+        const uint32_t b = spread8(pbits >> (8 * d));
+        sum[d] = pick(up, d) + pick(dn, d) + pick(mid, d) + horizontal(mid, d, halo, odd);
+        key[d] = s + s + b;                                   // n * 2 + b, at most 5 per nibble
+        const uint32_t v = s + 0x11111111u + b;               // n + 1 + b in 1..4
+        const uint32_t ge3 = ((v + 0x55555555u) & 0x88888888u) >> 3;
+        nxt[d] = v - (ge3 | (ge3 << 1));                      // mod 3
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int h = 1; h >= 0; --h) {
+        Philox4 P[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint64_t b = blk0 + 2 * d + h;
+            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
+        }
+#pragma unroll
+        for (int jj = 3; jj >= 0; --jj)
+#pragma unroll
+            for (int d = 3; d >= 0; --d) {
+                const int j = 4 * h + jj;
+                const uint32_t kj = (key[d] >> (4 * j)) & 0xFu;
+                const uint32_t sj = (sum[d] >> (4 * j)) & 0xFu;
+                uint32_t idx = kj * 16u + sj;
+                idx = idx < 95u ? idx : 95u;
+                const uint2 e = tab[idx];
+                const uint32_t u = philox_word(P[d], jj);
+                const uint64_t lhs = (uint64_t)u;
+                const uint64_t rhs = ((uint64_t)e.y << 32) | e.x;
+                acc = acc + acc + (uint32_t)(lhs < rhs);
+            }
+    }
+    uint32_t res[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t s = pick(src, d);
+        const uint32_t a = (acc >> d) & 0x11111111u;
+        const uint32_t mask = (a << 4) - a;                   // 0xF in accepted nibbles
+        res[d] = (s & ~mask) | (nxt[d] & mask);
+    }
+    return make_uint4(res[0], res[1], res[2], res[3]);
+}
+
+// Blume-Capel table in LDS, 96 entries indexed (n * 2 + b) * 16 + cell-sum:
+// x = threshold, y = 1 when dE <= 0 (always accept).  Unused slots (sum > 8,
+// n > 2) never accept.
+struct BCLds {
+    uint2 e[96];
+};
+
+__device__ __forceinline__ void load_bc_table(BCLds& lds, const BCTable& tbl)
+{
+    for (uint32_t i = threadIdx.x; i < 96u; i += blockDim.x) {
+        const uint32_t key = i >> 4, sj = i & 15u;
+        uint2 v = make_uint2(0u, 0u);
+        if (key < 6u && sj < 9u) {
+            const uint32_t n = key >> 1, b = key & 1u;
+            const uint32_t idx = (n * 2u + b) * 9u + sj;
+            v = make_uint2(tbl.thr[idx], tbl.always[idx] ? 1u : 0u);
+        }
+        lds.e[i] = v;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Half-sweep: one thread per 16-byte column vector, walking `rows` rows
+// (even, starting at an even row).  The colour is a template parameter, so
+// the parity of y + c, which picks the horizontal neighbours, is known at
+// compile time for the two rows of each unrolled pair.
+// ---------------------------------------------------------------------------
+struct RowState {
+    const uint4* pcur;      // other plane, row y, this column
+    uint4* pown;            // own plane, row y, this column
+    const uint32_t* hrow;   // other plane, row y, word 0
+    uint64_t blk;           // accept block of the vector's cell 0
+    uint64_t kv;            // in-colour index of the vector's cell 0
+    uint4 up, mid;
+};
+
+template <int MODEL, bool HI0, bool ODD>
+__device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__ oth_col0, uint32_t y, uint32_t L,
+                                         uint32_t Q, uint32_t W, uint32_t hwl, uint32_t hwr, uint32_t color,
+                                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8,
+                                         const uint2* tab)
+{
+    const uint4* pdn = (y + 1 == L) ? oth_col0 : st.pcur + Q;
+    const uint4 dn = *pdn;
+    const uint4 src = *st.pown;
+    const uint32_t halo = st.hrow[ODD ? hwr : hwl];
+    uint4 res;
+    if (MODEL == 0) {
+        res = ising_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, t, color, k0, k1, T4, T8);
+    } else {
+        const uint64_t pb = st.kv >> 7;
+        const Philox4 p = philox4x32_10(lo32(pb), HI0 ? 0u : hi32(pb), t, 2u + color, k0, k1);
+        const uint32_t pbits = philox_word(p, (int)((st.kv >> 5) & 3));
+        res = bc_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, pbits, t, color, k0, k1, tab);
+    }
+    *st.pown = res;
+    st.up = st.mid;
+    st.mid = dn;
+    st.pcur += Q;
+    st.pown += Q;
+    st.hrow += W;
+    st.blk += L >> 3;
+    st.kv += L >> 1;
+}
+
+template <int MODEL, bool HI0, int COLOR>
+__global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
+                                                         uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
+                                                         uint32_t k1, uint32_t T4, uint32_t T8, BCTable tbl)
+{
+    __shared__ BCLds s_tab;
+    if (MODEL == 1) load_bc_table(s_tab, tbl);
+    const uint32_t Q = L >> 6;
+    const uint32_t W = L >> 4;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t q = g % Q;
+    const uint32_t band = g / Q;
+    const uint32_t y0 = band * rows;
+    if (y0 >= L) return;
+    const uint4* __restrict__ oth4 = reinterpret_cast<const uint4*>(oth) + q;
+    RowState st;
+    st.pcur = oth4 + (size_t)y0 * Q;
+    st.pown = reinterpret_cast<uint4*>(own) + (size_t)y0 * Q + q;
+    st.hrow = oth + (size_t)y0 * W;
+    st.blk = ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2;
+    st.kv = (uint64_t)y0 * (L >> 1) + 32u * q;
+    st.up = *(oth4 + (size_t)(y0 == 0 ? L - 1 : y0 - 1) * Q);
+    st.mid = *st.pcur;
+    const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;         // word left of the vector
+    const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;     // word right of the vector
+    for (uint32_t r = 0; r < rows; r += 2) {
+        // even row y: parity of y + c is c; odd row: 1 - c
+        row_step<MODEL, HI0, COLOR == 1>(st, oth4, y0 + r, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8, s_tab.e);
+        row_step<MODEL, HI0, COLOR == 0>(st, oth4, y0 + r + 1, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8,
+                                         s_tab.e);
     }
 }
 
 int64_t band_rows(int64_t L)
 {
-    // rows per band: deep enough to amortise the two halo rows, shallow
-    // enough to give the chip many thousand waves
-    int64_t rows = 16;
-    while (rows > 1 && (L % rows) != 0) rows >>= 1;
-    return rows;
+    // even; deep enough to amortise the two halo rows (1/16 extra reads of
+    // the other plane at 32 rows), shallow enough for many thousand waves.
+    // L is a multiple of 64, so both choices divide it.
+    return L >= 4096 ? 32 : 16;
 }
 
 }  // namespace
@@ -216,6 +325,18 @@ hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, 
     return hipGetLastError();
 }
 
+template <int MODEL, bool HI0>
+static void launch_model(dim3 grid, hipStream_t s, uint32_t* own, const uint32_t* oth, uint32_t L, uint32_t R, int c,
+                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8, const BCTable& tbl)
+{
+    if (c == 0)
+        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, T4,
+                           T8, tbl);
+    else
+        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, T4,
+                           T8, tbl);
+}
+
 static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s, int model)
 {
     const int64_t rows = band_rows(g.L);
@@ -226,12 +347,17 @@ static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t
     uint32_t* own = g.plane(a.color);
     const uint32_t* oth = g.plane(1 - a.color);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    if (model == 0)
-        hipLaunchKernelGGL(half_sweep_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, s, own, oth, g.L, rows,
-                           (uint32_t)a.color, a.t, k0, k1, a.T4, a.T8, tbl);
-    else
-        hipLaunchKernelGGL(half_sweep_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, s, own, oth, g.L, rows,
-                           (uint32_t)a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+    // block indices fit 32 bits while L^2 / 8 <= 2^32
+    const bool hi0 = (g.L * g.L / 8) <= (int64_t(1) << 32);
+    const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
+    const dim3 grid((uint32_t)blocks);
+    if (model == 0) {
+        if (hi0) launch_model<0, true>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+        else launch_model<0, false>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+    } else {
+        if (hi0) launch_model<1, true>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+        else launch_model<1, false>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+    }
     return hipGetLastError();
 }
 
