@@ -158,11 +158,29 @@ int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t);
 int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, int64_t* t);
 
 /* a9 -- Batched path: advance `count` independent lattices (any mix of
- * models, sizes, beta and D) by n[i] sweeps each.  All lattices must share
- * the stream of hs[0].  Replicas advance sweep by sweep together; every
- * lattice ends bit-identical to n[i] sweep() calls on it alone. */
+ * models, sizes, beta and D) by n[i] sweeps each.  Replicas advance sweep by
+ * sweep together: one launch per model and colour covers every replica
+ * (each workgroup belongs to one replica, so its parameters are
+ * wave-uniform).  All lattices must use the stream of hs[0] (MCL_EARG
+ * otherwise).  Every lattice ends bit-identical to n[i] sweep() calls on it
+ * alone, whatever the tuning.  The library keeps a few small workspaces of
+ * its own (descriptors, pinned staging, captured graphs), allocated on first
+ * use and grown when a larger group arrives; they are never freed. */
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n,
                 const double* beta, const double* D);
+
+/* Tuning of group_sweep, process-wide; chosen by the package's autotuner.
+ * rows_log2L[k]: band height (rows per thread, one of 8, 16, 32, 64) for
+ * lattices with 2^k <= L < 2^(k+1); use_graph: capture the call's launches
+ * in a hipGraph and replay it (cached per group shape); largest_first:
+ * dispatch the largest replicas first.  Results never depend on it. */
+typedef struct mcl_group_tuning {
+    int32_t rows_log2L[21];
+    int32_t use_graph;
+    int32_t largest_first;
+} mcl_group_tuning;
+int mcl_group_tuning_get(mcl_group_tuning* out);
+int mcl_group_tuning_set(const mcl_group_tuning* in);   /* MCL_EARG on an invalid row count */
 
 /* Release a handle (does not free the caller's device memory). */
 int lattice_free(mcl_lattice* h);

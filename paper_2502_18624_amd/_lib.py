@@ -43,6 +43,11 @@ class MeasureOut(ctypes.Structure):
     ]
 
 
+class GroupTuning(ctypes.Structure):
+    _fields_ = [("rows_log2L", ctypes.c_int32 * 21), ("use_graph", ctypes.c_int32),
+                ("largest_first", ctypes.c_int32)]
+
+
 # Every entry point of include/mcl.h with its ctypes signature.
 _P = ctypes.c_void_p
 _I64, _U64, _I32, _U32, _INT, _DBL = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
@@ -63,6 +68,8 @@ SIGNATURES = {
                             ctypes.POINTER(_I64)]),
     "group_sweep": (_INT, [ctypes.POINTER(_P), _INT, ctypes.POINTER(_I64), ctypes.POINTER(_DBL),
                            ctypes.POINTER(_DBL)]),
+    "mcl_group_tuning_get": (_INT, [ctypes.POINTER(GroupTuning)]),
+    "mcl_group_tuning_set": (_INT, [ctypes.POINTER(GroupTuning)]),
     "lattice_free": (_INT, [_P]),
     "mcl_strerror": (ctypes.c_char_p, [_INT]),
     "mcl_last_hip_error": (_INT, []),

@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mcl.h"
@@ -20,6 +23,8 @@ struct mcl_lattice {
     int32_t* rdev;       // device: distances, rcap entries
     int64_t* Cx;         // device: rcap entries
     int64_t* Cy;         // device: rcap entries
+    int32_t* res;        // device: 17 offsets + rcap positions, sampled distances grouped by r mod 16
+    int8_t* zs;          // device: (L/16)^2 sampled sources as int8
     int64_t rcap;
     hipStream_t stream;
 };
@@ -47,7 +52,7 @@ bool valid_L(int64_t L) { return L >= 64 && (L % 64) == 0 && L <= (int64_t(1) <<
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-    int64_t planes, acc, rlist, cx, cy, total, rcap;
+    int64_t planes, acc, rlist, cx, cy, res, zs, total, rcap;
 };
 
 Layout layout_of(int64_t L)
@@ -65,6 +70,10 @@ Layout layout_of(int64_t L)
     off += align256(lay.rcap * 8);
     lay.cy = off;
     off += align256(lay.rcap * 8);
+    lay.res = off;
+    off += align256((lay.rcap + 17) * 4);
+    lay.zs = off;
+    off += align256((L / 16) * (L / 16));
     lay.total = off;
     return lay;
 }
@@ -141,6 +150,228 @@ int check_params(const mcl_lattice* h, double beta, double D)
 }
 
 int8_t cell_to_spin(uint32_t word, int64_t i) { return (int8_t)((int)((word >> (4 * (i & 7))) & 0xFu) - 1); }
+
+// ---------------------------------------------------------------------------
+// Batched path (row a9).
+// ---------------------------------------------------------------------------
+mcl_group_tuning default_tuning()
+{
+    mcl_group_tuning t;
+    for (int k = 0; k < 21; ++k) t.rows_log2L[k] = k >= 12 ? 32 : 16;
+    t.use_graph = 0;
+    t.largest_first = 1;
+    return t;
+}
+
+std::mutex g_group_mu;
+mcl_group_tuning g_tuning = default_tuning();
+
+// A staging slot: pinned host buffer and device buffer for one call's
+// descriptors and tables, and an event recorded after the call's last
+// launch; a slot is reused only after that event completed, so neither
+// buffer is overwritten while a copy or kernel still reads it.
+struct Slot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kSlots = 4;
+struct DeviceSlots {
+    Slot slot[kSlots];
+    int next = 0;
+};
+std::map<int, DeviceSlots> g_slots;
+
+// Captured graphs, keyed by the call's shape (descriptor buffer, replica
+// counts, workgroup counts, sweeps).
+using GraphKey = std::tuple<void*, int, int, uint32_t, uint32_t, int64_t>;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// Graph capture is not allowed on the null stream, which is where a caller
+// on PyTorch's default stream queues its work; such calls capture and
+// replay on a library stream (default priority) fenced by events.
+struct CaptureStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;
+};
+std::map<int, CaptureStream> g_capture;
+
+int log2_floor(int64_t v)
+{
+    int k = 0;
+    while ((int64_t(1) << (k + 1)) <= v) ++k;
+    return k;
+}
+
+// Blume-Capel table in the kernel's LDS order: 96 entries indexed
+// (n * 2 + b) * 16 + neighbour-cell-sum, x = threshold, y = always.
+void bc_lds_table(double beta, double D, uint32_t* out /* 192 words */)
+{
+    mcl::BCTable tb;
+    bc_table(beta, D, tb);
+    for (int i = 0; i < 96; ++i) {
+        const int key = i >> 4, sj = i & 15;
+        uint32_t thr = 0, alw = 0;
+        if (key < 6 && sj < 9) {
+            const int idx = key * 9 + sj;        // ((n * 2 + b) * 9 + sum)
+            thr = tb.thr[idx];
+            alw = tb.always[idx] ? 1u : 0u;
+        }
+        out[2 * i] = thr;
+        out[2 * i + 1] = alw;
+    }
+}
+
+int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
+{
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    const mcl_group_tuning tun = g_tuning;
+    hipStream_t stream = hs[0]->stream;
+    int devid = 0;
+    MCL_HIP(hipGetDevice(&devid));
+
+    // replicas with work, per model, optionally largest first
+    std::vector<int> idx[2];
+    int64_t nmax = 0;
+    for (int i = 0; i < count; ++i)
+        if (n[i] > 0) {
+            idx[hs[i]->model].push_back(i);
+            nmax = std::max(nmax, n[i]);
+        }
+    if (nmax == 0) return MCL_OK;
+    for (int m = 0; m < 2; ++m)
+        if (tun.largest_first)
+            std::stable_sort(idx[m].begin(), idx[m].end(), [&](int a, int b) { return hs[a]->L > hs[b]->L; });
+
+    const size_t ndesc = idx[0].size() + idx[1].size();
+    const size_t bytes = ndesc * sizeof(mcl::GroupDesc) + idx[1].size() * 96 * sizeof(uint2);
+
+    DeviceSlots& ds = g_slots[devid];
+    Slot& sl = ds.slot[ds.next];
+    ds.next = (ds.next + 1) % kSlots;
+    if (sl.pending) {
+        MCL_HIP(hipEventSynchronize(sl.done));
+        sl.pending = false;
+    }
+    if (!sl.done) MCL_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    if (sl.cap < bytes) {
+        // graphs captured against the old device buffer are dropped with it
+        for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+            if (std::get<0>(it->first) == sl.dev) {
+                hipGraphExecDestroy(it->second);
+                it = g_graphs.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if (sl.host) MCL_HIP(hipHostFree(sl.host));
+        if (sl.dev) MCL_HIP(hipFree(sl.dev));
+        sl.host = sl.dev = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
+        MCL_HIP(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
+        MCL_HIP(hipMalloc(&sl.dev, cap));
+        sl.cap = cap;
+    }
+
+    mcl::GroupDesc* hd = (mcl::GroupDesc*)sl.host;
+    uint32_t* htab = (uint32_t*)(hd + ndesc);
+    uint32_t wgs[2] = {0, 0};
+    int nb = 0;
+    size_t k = 0;
+    for (int m = 0; m < 2; ++m)
+        for (int i : idx[m]) {
+            const mcl_lattice* h = hs[i];
+            mcl::GroupDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.plane0 = h->g.plane0;
+            d.L = (uint32_t)h->L;
+            d.rows = (uint32_t)tun.rows_log2L[log2_floor(h->L)];
+            d.hi0 = (h->L * h->L / 8) <= (int64_t(1) << 32) ? 1u : 0u;
+            d.t0 = (uint32_t)h->t;
+            d.n = (uint32_t)n[i];
+            d.k0 = (uint32_t)h->seed;
+            d.k1 = (uint32_t)(h->seed >> 32);
+            if (m == 0) {
+                ising_thresholds(beta[i], d.T4, d.T8);
+            } else {
+                d.bc = (uint32_t)nb;
+                bc_lds_table(beta[i], D[i], htab + (size_t)nb * 192);
+                ++nb;
+            }
+            const int64_t threads = h->g.Q * (h->L / d.rows);
+            d.wg_begin = wgs[m];
+            wgs[m] += (uint32_t)((threads + 255) / 256);
+            hd[k++] = d;
+        }
+    MCL_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
+    const mcl::GroupDesc* ddesc[2] = {(const mcl::GroupDesc*)sl.dev,
+                                      (const mcl::GroupDesc*)sl.dev + idx[0].size()};
+    const uint2* dtab = (const uint2*)((const mcl::GroupDesc*)sl.dev + ndesc);
+    const int cnt[2] = {(int)idx[0].size(), (int)idx[1].size()};
+
+    auto launch_all = [&]() -> hipError_t {
+        for (int64_t s = 0; s < nmax; ++s)
+            for (int c = 0; c < 2; ++c)
+                for (int m = 0; m < 2; ++m) {
+                    const hipError_t e = mcl::launch_group_half(m, c, ddesc[m], cnt[m], wgs[m], dtab,
+                                                                (uint32_t)s, stream);
+                    if (e != hipSuccess) return e;
+                }
+        return hipSuccess;
+    };
+
+    if (tun.use_graph && nmax > 1) {
+        hipStream_t gs = stream;
+        CaptureStream* cs = nullptr;
+        if (stream == nullptr) {
+            cs = &g_capture[devid];
+            if (!cs->stream) {
+                MCL_HIP(hipStreamCreateWithFlags(&cs->stream, hipStreamNonBlocking));
+                MCL_HIP(hipEventCreateWithFlags(&cs->in, hipEventDisableTiming));
+                MCL_HIP(hipEventCreateWithFlags(&cs->out, hipEventDisableTiming));
+            }
+            gs = cs->stream;
+            MCL_HIP(hipEventRecord(cs->in, stream));
+            MCL_HIP(hipStreamWaitEvent(gs, cs->in, 0));
+        }
+        const GraphKey key{sl.dev, cnt[0], cnt[1], wgs[0], wgs[1], nmax};
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            MCL_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+            hipError_t le = hipSuccess;
+            for (int64_t s = 0; s < nmax && le == hipSuccess; ++s)
+                for (int c = 0; c < 2 && le == hipSuccess; ++c)
+                    for (int m = 0; m < 2 && le == hipSuccess; ++m)
+                        le = mcl::launch_group_half(m, c, ddesc[m], cnt[m], wgs[m], dtab, (uint32_t)s, gs);
+            const hipError_t ce = hipStreamEndCapture(gs, &graph);
+            if (le != hipSuccess) return hip_fail(le);
+            if (ce != hipSuccess) return hip_fail(ce);
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ie != hipSuccess) return hip_fail(ie);
+            if (g_graphs.size() >= 32) {
+                hipGraphExecDestroy(g_graphs.begin()->second);
+                g_graphs.erase(g_graphs.begin());
+            }
+            it = g_graphs.emplace(key, exec).first;
+        }
+        MCL_HIP(hipGraphLaunch(it->second, gs));
+        if (cs) {
+            MCL_HIP(hipEventRecord(cs->out, gs));
+            MCL_HIP(hipStreamWaitEvent(stream, cs->out, 0));
+        }
+    } else {
+        MCL_HIP(launch_all());
+    }
+    MCL_HIP(hipEventRecord(sl.done, stream));
+    sl.pending = true;
+    return MCL_OK;
+}
 
 }  // namespace
 
@@ -236,6 +467,8 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->rdev = (int32_t*)(base + lay.rlist);
     h->Cx = (int64_t*)(base + lay.cx);
     h->Cy = (int64_t*)(base + lay.cy);
+    h->res = (int32_t*)(base + lay.res);
+    h->zs = (int8_t*)(base + lay.zs);
     h->rcap = lay.rcap;
     h->stream = (hipStream_t)hip_stream;
     const hipError_t e = mcl::launch_init(h->g, model, init_state, seed, h->stream);
@@ -316,10 +549,44 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         MCL_HIP(mcl::launch_zero(h->Cy, nr, h->stream));
     }
     MCL_HIP(mcl::launch_bmq(h->g, h->acc, h->stream));
+    // The host buffer of residue lists must outlive the asynchronous copy:
+    // it lives until the synchronisation below.
+    std::vector<int32_t> res;
     if (nr > 0) {
-        MCL_HIP(mcl::launch_corr_all(h->g, h->rdev, n_all, h->Cx, h->Cy, h->stream));
-        MCL_HIP(mcl::launch_corr_sampled(h->g, h->rdev + n_all, nr - n_all, h->Cx + n_all, h->Cy + n_all,
-                                         h->stream));
+        // every-source distances are r = 0 .. n_all - 1 (position j holds r = j)
+        const int rshort = std::min(n_all - 1, 32);
+        MCL_HIP(mcl::launch_corr_short(h->g, h->model, rshort, h->Cx, h->Cy, h->stream));
+        if (n_all - 1 > 32)
+            MCL_HIP(mcl::launch_corr_all(h->g, h->rdev + 33, n_all - 33, h->Cx + 33, h->Cy + 33, h->stream));
+        const int ns = nr - n_all;
+        if (ns > 0) {
+            // group the sampled distances by r mod 16 (positions within the sampled sub-list)
+            res.assign(17 + ns, 0);
+            int maxc = 0;
+            for (int rho = 0, pos = 17; rho < 16; ++rho) {
+                res[rho] = pos - 17;
+                int cnt = 0;
+                for (int j = 0; j < ns; ++j)
+                    if ((r[n_all + j] & 15) == rho) {
+                        res[pos++] = j;
+                        ++cnt;
+                    }
+                maxc = std::max(maxc, cnt);
+            }
+            res[16] = ns;
+            MCL_HIP(hipMemcpyAsync(h->res, res.data(), res.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   h->stream));
+            mcl::SampledArgs sa;
+            sa.r = h->rdev + n_all;
+            sa.nr = ns;
+            sa.Cx = h->Cx + n_all;
+            sa.Cy = h->Cy + n_all;
+            sa.zs = h->zs;
+            sa.res_off = h->res;
+            sa.res_idx = h->res + 17;
+            sa.max_per_residue = maxc;
+            MCL_HIP(mcl::launch_corr_sampled(h->g, sa, h->stream));
+        }
     }
     int64_t acc[mcl::kAccSlots];
     MCL_HIP(hipMemcpyAsync(acc, h->acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
@@ -334,7 +601,7 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
     out->counts[0] = acc[3];
     out->counts[1] = acc[4];
     out->counts[2] = acc[2];
-    out->invalid = acc[5];
+    out->invalid = h->L * h->L - acc[2] - acc[3] - acc[4];
     out->t = h->t;
     const int64_t all_src = h->L * h->L;
     const int64_t sampled_src = (h->L / 16) * (h->L / 16);
@@ -428,20 +695,37 @@ int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t)
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
 {
     if (count < 0 || (count > 0 && (!hs || !n || !beta || !D))) return MCL_EARG;
-    int64_t nmax = 0;
+    if (count == 0) return MCL_OK;
     for (int i = 0; i < count; ++i) {
         if (!hs[i] || n[i] < 0) return MCL_EARG;
+        if (hs[i]->stream != hs[0]->stream) return MCL_EARG;
         const int pc = check_params(hs[i], beta[i], D[i]);
         if (pc) return pc;
         if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
-        nmax = std::max(nmax, n[i]);
     }
-    for (int64_t s = 0; s < nmax; ++s)
-        for (int i = 0; i < count; ++i)
-            if (n[i] > s) {
-                const int rc = sweep(hs[i], 1, beta[i], D[i]);
-                if (rc) return rc;
-            }
+    const int rc = group_run(hs, count, n, beta, D);
+    if (rc) return rc;
+    for (int i = 0; i < count; ++i) hs[i]->t += n[i];
+    return MCL_OK;
+}
+
+int mcl_group_tuning_get(mcl_group_tuning* out)
+{
+    if (!out) return MCL_EARG;
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    *out = g_tuning;
+    return MCL_OK;
+}
+
+int mcl_group_tuning_set(const mcl_group_tuning* in)
+{
+    if (!in) return MCL_EARG;
+    for (int k = 0; k < 21; ++k) {
+        const int r = in->rows_log2L[k];
+        if (r != 8 && r != 16 && r != 32 && r != 64) return MCL_EARG;
+    }
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    g_tuning = *in;
     return MCL_OK;
 }
 

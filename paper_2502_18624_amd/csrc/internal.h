@@ -34,15 +34,46 @@ hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 
 // a6 / a7: measurement kernels accumulating into int64 device scratch.
 // acc layout: [0] B, [1] M (from +1 count minus -1 count), [2] #(+1),
-// [3] #(-1), [4] #(0), [5] invalid cells, [6..14] reserved.
+// [3] #(-1), [4] #(0), [5..15] reserved; cells that are none of the three
+// (corrupted) are L^2 minus the three counts.
 constexpr int kAccSlots = 16;
 hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s);
-// Correlations from every source at distances r[0..nr).
+// Correlations from every source at r = 0..R (R <= 32), LDS-tiled.
+hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s);
+// Correlations from every source at distances r[0..nr) (any r <= L/2).
 hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
                            hipStream_t s);
 // Correlations from the sampled sources x = y = 0 (mod 16) at r[0..nr).
-hipError_t launch_corr_sampled(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
-                               hipStream_t s);
+// res_off[17] / res_idx group the positions j of the distances by r_j mod 16.
+struct SampledArgs {
+    const int32_t* r;
+    int nr;
+    int64_t* Cx;
+    int64_t* Cy;
+    int8_t* zs;              // (L/16)^2 bytes of scratch
+    const int32_t* res_off;
+    const int32_t* res_idx;
+    int max_per_residue;
+};
+hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s);
+
+// a9: batched half-sweep.  One descriptor per replica (64 bytes).
+struct GroupDesc {
+    uint32_t* plane0;      // the replica's planes (P_1 follows P_0)
+    uint32_t L;
+    uint32_t rows;         // band rows: even, divides L
+    uint32_t hi0;          // 1 when every accept block index fits 32 bits
+    uint32_t t0;           // sweep counter at the start of the call
+    uint32_t n;            // sweeps for this replica in this call
+    uint32_t k0, k1;       // Philox key (seed)
+    uint32_t T4, T8;       // Ising thresholds
+    uint32_t wg_begin;     // first workgroup of this replica in its launch
+    uint32_t bc;           // index of its Blume-Capel table (96 entries)
+    uint32_t pad[3];
+};
+static_assert(sizeof(GroupDesc) == 64, "descriptor size");
+hipError_t launch_group_half(int model, int color, const GroupDesc* desc, int count, uint32_t total_wgs,
+                             const uint2* tables, uint32_t s, hipStream_t st);
 
 }  // namespace mcl

@@ -4,7 +4,8 @@
 // a colour-1 site (L even), so the bond sum B is the sum over colour-0 cells
 // of s times the sum of its four neighbours; products of two cells are
 // counted eight at a time with popcounts (cell n = s + 1: a product is
-// nonzero iff neither cell is 1, and +1 iff bit 1 agrees).
+// nonzero iff neither cell is 1, and +1 iff bit 1 agrees; Ising cells are
+// never 1, so there a word pair needs one xor-and and one popcount).
 //
 // Correlations (section 3.3).  For a source at (x, y) in plane c:
 //   along y the partner (x, y + r) is in plane c ^ (r & 1), row y + r, same
@@ -12,8 +13,14 @@
 //   along x the partner (x + r, y) is in plane c ^ (r & 1) at in-plane index
 //   i + m with m = r / 2 (r even) or (r - 1) / 2 + ((y + c) & 1) (r odd), a
 //   funnel shift of two neighbouring words.
-// The sampled sources (x = y = 0 mod 16) are cell 0 of every word of the
-// rows y = 0 mod 16 of plane 0.
+// Every-source distances r <= 32 run from an LDS tile of both planes with 32
+// halo rows; longer every-source distances (full mode) read partners from
+// global memory.  The sampled sources (x = y = 0 mod 16) are cell 0 of
+// every word of the rows y = 0 mod 16 of plane 0: along x each source row is
+// unpacked to one int8 per site in LDS; along y the work runs over target
+// rows against a compact int8 copy of the sources, four products per dot4.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mcl {
@@ -25,85 +32,259 @@ __global__ void zero_kernel(int64_t* p, int64_t n)
     if (i < n) p[i] = 0;
 }
 
-__device__ __forceinline__ void cell_counts(uint32_t w, int64_t& np1, int64_t& nm1, int64_t& n0, int64_t& ninv)
-{
-    const uint32_t b1 = w >> 1, b2 = w >> 2, b3 = w >> 3;
-    const uint32_t high = (b2 | b3);
-    const uint32_t m1 = ~(w | b1 | high) & 0x11111111u;
-    const uint32_t z = (w & ~(b1 | high)) & 0x11111111u;
-    const uint32_t p1 = (b1 & ~w & ~high) & 0x11111111u;
-    const uint32_t a = popc(p1), b = popc(m1), c = popc(z);
-    np1 += a;
-    nm1 += b;
-    n0 += c;
-    ninv += 8 - (a + b + c);
-}
-
 __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 {
     return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
 }
 
-__global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
-                                                  int64_t L, int64_t rows, int64_t* __restrict__ acc)
+__device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n ? v - n : v; }
+
+// Per-word cell counts: +1 (n = 2), -1 (n = 0), 0 (n = 1), anything else.
+__device__ __forceinline__ void cell_counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
 {
-    const int64_t Q = L >> 6, W = L >> 4;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t q = g % Q;
-    const int64_t band = g / Q;
-    const int64_t y0 = band * rows;
-    int64_t B = 0, np1 = 0, nm1 = 0, n0 = 0, ninv = 0;
-    if (y0 < L) {
-        const uint4* a4 = reinterpret_cast<const uint4*>(p0);
-        const uint4* b4 = reinterpret_cast<const uint4*>(p1);
-        for (int64_t r = 0; r < rows; ++r) {
-            const int64_t y = y0 + r;
-            const int64_t yu = (y == 0) ? L - 1 : y - 1;
-            const int64_t yd = (y + 1 == L) ? 0 : y + 1;
-            const uint4 own = a4[y * Q + q];
-            const uint4 mid = b4[y * Q + q];
-            const uint4 up = b4[yu * Q + q];
-            const uint4 dn = b4[yd * Q + q];
-            const uint32_t odd = (uint32_t)(y & 1);
-            const int64_t hw = odd ? ((4 * q + 4 == W) ? 0 : 4 * q + 4) : ((q == 0) ? W - 1 : 4 * q - 1);
-            const uint32_t halo = p1[y * W + hw];
+    const uint32_t b1 = w >> 1, high = (w >> 2) | (w >> 3);
+    np1 += popc((b1 & ~w & ~high) & 0x11111111u);
+    nm1 += popc(~(w | b1 | high) & 0x11111111u);
+    n0 += popc((w & ~(b1 | high)) & 0x11111111u);
+}
+
+// Sum of s * s' over the 8 cell pairs of two words, as (nonzero pairs,
+// pairs of opposite sign): the sum is nz - 2 * diff.
+__device__ __forceinline__ void pair_counts(uint32_t a, uint32_t b, uint32_t& nz, uint32_t& diff)
+{
+    const uint32_t z = ~(a | b) & 0x11111111u;
+    nz += popc(z);
+    diff += popc(((a ^ b) >> 1) & z);
+}
+
+// Sum v[0..N) over the workgroup (wave sums, then across the waves in LDS)
+// and add the totals to out[0..N): one atomic per value per workgroup, so
+// the device-wide atomics on a handful of addresses stay few.
+template <int N>
+__device__ __forceinline__ void block_add(const int64_t (&v)[N], int64_t* __restrict__ out, int64_t (*lds)[N])
+{
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int64_t s = wave_sum(v[i]);
+        if ((threadIdx.x & 63) == 0) lds[wave][i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        int64_t tot = 0;
+        for (int w = 0; w < nwaves; ++w) tot += lds[w][i];
+        if (tot != 0) atomicAdd((unsigned long long*)&out[i], (unsigned long long)tot);
+    }
+    __syncthreads();
+}
+
+// As block_add for 2 N values: v[0..N) go to X, v[N..2N) to Y.
+template <int N>
+__device__ __forceinline__ void block_add_xy(const int64_t (&v)[2 * N], int64_t* __restrict__ X,
+                                             int64_t* __restrict__ Y, int64_t (*lds)[2 * N])
+{
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 2 * N; ++i) {
+        const int64_t s = wave_sum(v[i]);
+        if ((threadIdx.x & 63) == 0) lds[wave][i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+        int64_t tot = 0;
+        for (int w = 0; w < nwaves; ++w) tot += lds[w][i];
+        int64_t* dst = i < N ? &X[i] : &Y[i - N];
+        if (tot != 0) atomicAdd((unsigned long long*)dst, (unsigned long long)tot);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// a6: B, M, Q, counts.  One thread per 16-byte column of plane 0, walking a
+// band of rows with plane 1's rows y - 1, y, y + 1 in registers.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
+                                                  uint32_t L, uint32_t rows, int64_t* __restrict__ acc)
+{
+    __shared__ int64_t red[4][5];
+    const uint32_t Q = L >> 6, W = L >> 4;
+    const uint32_t tasks = Q * (L / rows);
+    uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < tasks; g += gridDim.x * blockDim.x) {
+        const uint32_t q = g % Q;
+        const uint32_t y0 = (g / Q) * rows;
+        const uint4* a4 = reinterpret_cast<const uint4*>(p0) + q;
+        const uint4* b4 = reinterpret_cast<const uint4*>(p1) + q;
+        uint4 up = b4[(size_t)(y0 == 0 ? L - 1 : y0 - 1) * Q];
+        uint4 mid = b4[(size_t)y0 * Q];
+        const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;
+        const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;
+        for (uint32_t r = 0; r < rows; ++r) {
+            const uint32_t y = y0 + r;
+            const uint32_t yd = (y + 1 == L) ? 0 : y + 1;
+            const uint4 own = a4[(size_t)y * Q];
+            const uint4 dn = b4[(size_t)yd * Q];
+            const bool odd = (y & 1u) != 0;
+            const uint32_t halo = p1[(size_t)y * W + (odd ? hwr : hwl)];
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 const uint32_t w = pick(mid, d);
-                uint32_t hs;
-                if (odd)
-                    hs = funnel(d < 3 ? pick(mid, d + 1) : halo, w, 4);
-                else
-                    hs = funnel(w, d > 0 ? pick(mid, d - 1) : halo, 28);
+                const uint32_t hs = odd ? funnel(d < 3 ? pick(mid, d + 1) : halo, w, 4)
+                                        : funnel(w, d > 0 ? pick(mid, d - 1) : halo, 28);
                 const uint32_t o = pick(own, d);
-                B += pair_products(o, pick(up, d)) + pair_products(o, pick(dn, d)) + pair_products(o, w) +
-                     pair_products(o, hs);
-                cell_counts(o, np1, nm1, n0, ninv);
-                cell_counts(w, np1, nm1, n0, ninv);
+                pair_counts(o, pick(up, d), nz, diff);
+                pair_counts(o, pick(dn, d), nz, diff);
+                pair_counts(o, w, nz, diff);
+                pair_counts(o, hs, nz, diff);
+                cell_counts(o, np1, nm1, n0);
+                cell_counts(w, np1, nm1, n0);
             }
+            up = mid;
+            mid = dn;
         }
     }
-    B = wave_sum(B);
-    np1 = wave_sum(np1);
-    nm1 = wave_sum(nm1);
-    n0 = wave_sum(n0);
-    ninv = wave_sum(ninv);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long*)&acc[0], (unsigned long long)B);
-        atomicAdd((unsigned long long*)&acc[1], (unsigned long long)(np1 - nm1));
-        atomicAdd((unsigned long long*)&acc[2], (unsigned long long)np1);
-        atomicAdd((unsigned long long*)&acc[3], (unsigned long long)nm1);
-        atomicAdd((unsigned long long*)&acc[4], (unsigned long long)n0);
-        atomicAdd((unsigned long long*)&acc[5], (unsigned long long)ninv);
+    // acc: [0] B, [1] M, [2] #(+1), [3] #(-1), [4] #(0); invalid cells are
+    // what the three counts leave of L^2 (done on the host)
+    const int64_t v[5] = {(int64_t)nz - 2 * (int64_t)diff, (int64_t)np1 - (int64_t)nm1, (int64_t)np1,
+                          (int64_t)nm1, (int64_t)n0};
+    block_add<5>(v, acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// a7, every source, r = 0..R (R <= 32): LDS tile of SW columns (+1 halo
+// column on the right for x-partners) by TH source rows (+32 halo rows
+// below for y-partners), both planes.  Thread (j, g) handles column j and
+// rows 4g .. 4g + 3 of the tile, for r in [RLO, RHI].
+// ---------------------------------------------------------------------------
+constexpr int kSW = 32;
+constexpr int kTH = 32;
+constexpr int kHalo = 32;
+constexpr int kTileRows = kTH + kHalo;
+
+struct ShortTile {
+    uint4 v[2][kTileRows][kSW + 1];
+};
+
+// Adds s * s' summed over the 8 cell pairs of two words to acc, except for
+// the Ising model, where every product is nonzero and acc counts the pairs
+// of opposite sign (the sum is then pairs - 2 acc).
+template <int MODEL>
+__device__ __forceinline__ void pair_acc(uint32_t a, uint32_t b, int& acc)
+{
+    if (MODEL == 0) {
+        acc += (int)popc((a ^ b) & 0x22222222u);
+    } else {
+        const uint32_t z = ~(a | b) & 0x11111111u;
+        acc += (int)popc(z) - 2 * (int)popc(((a ^ b) >> 1) & z);
     }
 }
 
+template <int MODEL, int RLO, int RHI, int C, int PAR>
+__device__ __forceinline__ void short_row(const ShortTile& T, int lr, int j, int (&ax)[33], int (&ay)[33])
+{
+    const uint4 v = T.v[C][lr][j];
+    uint32_t w[2][7];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const uint4 a = T.v[p][lr][j], b = T.v[p][lr][j + 1];
+        w[p][0] = a.x; w[p][1] = a.y; w[p][2] = a.z; w[p][3] = a.w;
+        w[p][4] = b.x; w[p][5] = b.y; w[p][6] = b.z;
+    }
+#pragma unroll
+    for (int r = RLO; r <= RHI; ++r) {
+        const int pc = C ^ (r & 1);
+        const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);
+        const uint4 py = T.v[pc][lr + r][j];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t o = pick(v, d);
+            const int base = d + (m >> 3);
+            const uint32_t px = (m & 7) ? funnel(w[pc][base + 1], w[pc][base], 4 * (m & 7)) : w[pc][base];
+            pair_acc<MODEL>(o, px, ax[r]);
+            pair_acc<MODEL>(o, pick(py, d), ay[r]);
+        }
+    }
+}
+
+// Distances [RLO, RHI] over the thread's 4 rows of the current tile.
+template <int MODEL, int RLO, int RHI>
+__device__ __forceinline__ void short_chunk(const ShortTile& T, int j, int g, int (&ax)[33], int (&ay)[33])
+{
+    // tile rows 4g .. 4g + 3; the tile's first row is even, so the parity of
+    // y + c is that of the local row + c
+    for (int k = 0; k < 4; k += 2) {
+        const int lr = 4 * g + k;
+        short_row<MODEL, RLO, RHI, 0, 0>(T, lr, j, ax, ay);
+        short_row<MODEL, RLO, RHI, 1, 1>(T, lr, j, ax, ay);
+        short_row<MODEL, RLO, RHI, 0, 1>(T, lr + 1, j, ax, ay);
+        short_row<MODEL, RLO, RHI, 1, 0>(T, lr + 1, j, ax, ay);
+    }
+}
+
+// Persistent over tiles: each workgroup loads tiles (strip of kSW columns by
+// kTH rows, both planes, with halos) in turn and keeps its per-distance sums
+// in registers; one atomic per value per workgroup at the end.
+template <int MODEL>
+__global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restrict__ planes, uint32_t L, int R,
+                                                         int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
+{
+    __shared__ ShortTile T;
+    __shared__ int64_t red[4][66];
+    const uint32_t Q = L >> 6;
+    const uint32_t nstrips = (Q + kSW - 1) / kSW;
+    const uint32_t ntiles = nstrips * (L / kTH);
+    const size_t plane_vecs = (size_t)L * Q;
+    const uint4* P4 = reinterpret_cast<const uint4*>(planes);
+    const int j = threadIdx.x & (kSW - 1);
+    const int g = threadIdx.x / kSW;
+    int ax[33], ay[33];
+#pragma unroll
+    for (int k = 0; k < 33; ++k) ax[k] = ay[k] = 0;
+    int64_t pairs = 0;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t q0 = (tile % nstrips) * kSW;
+        const uint32_t y0 = (tile / nstrips) * kTH;
+        __syncthreads();
+        for (uint32_t idx = threadIdx.x; idx < 2u * kTileRows * (kSW + 1); idx += blockDim.x) {
+            const uint32_t c = idx / (kTileRows * (kSW + 1));
+            const uint32_t rem = idx - c * (kTileRows * (kSW + 1));
+            const uint32_t row = rem / (kSW + 1);
+            const uint32_t col = rem - row * (kSW + 1);
+            uint32_t y = y0 + row;
+            while (y >= L) y -= L;
+            uint32_t qq = q0 + col;
+            while (qq >= Q) qq -= Q;
+            T.v[c][row][col] = P4[c * plane_vecs + (size_t)y * Q + qq];
+        }
+        __syncthreads();
+        if (q0 + (uint32_t)j < Q) {
+            short_chunk<MODEL, 0, 10>(T, j, g, ax, ay);
+            if (R > 10) short_chunk<MODEL, 11, 21>(T, j, g, ax, ay);
+            if (R > 21) short_chunk<MODEL, 22, 32>(T, j, g, ax, ay);
+            pairs += 256;          // 4 rows x 2 planes x 32 cells per distance
+        }
+    }
+    int64_t v[66];
+#pragma unroll
+    for (int k = 0; k < 33; ++k) {
+        const bool on = k <= R;
+        v[k] = !on ? 0 : (MODEL == 0 ? pairs - 2 * (int64_t)ax[k] : (int64_t)ax[k]);
+        v[33 + k] = !on ? 0 : (MODEL == 0 ? pairs - 2 * (int64_t)ay[k] : (int64_t)ay[k]);
+    }
+    block_add_xy<33>(v, Cx, Cy, red);
+}
+
+// ---------------------------------------------------------------------------
+// a7, every source, arbitrary r (full mode beyond r = 32): partners read
+// from global memory.  One thread per (plane, band of rows, column), a
+// chunk of up to kRChunk distances per grid row.
+// ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
 
-__device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n ? v - n : v; }
-
 // Word of cells i + m .. i + m + 7 (periodic in the row of W words), where
-// cell i is cell 0 of word wd; m < 8 W.
+// cell i is cell 0 of word wd; wd + m / 8 < 2 W.
 __device__ __forceinline__ uint32_t shifted_word(const uint32_t* __restrict__ row, uint32_t W, uint32_t wd, uint32_t m)
 {
     const uint32_t w0 = wrap(wd + (m >> 3), W);
@@ -111,8 +292,6 @@ __device__ __forceinline__ uint32_t shifted_word(const uint32_t* __restrict__ ro
     return funnel(row[w1], row[w0], 4 * (m & 7));
 }
 
-// Every source: one thread per (plane, band of rows, 16-byte column), a
-// chunk of up to kRChunk distances per grid row.
 __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restrict__ planes, uint32_t L, uint32_t rows,
                                                        const int32_t* __restrict__ rlist, int nr,
                                                        int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
@@ -126,9 +305,9 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
     const uint32_t c = rest / nbands;
     const uint32_t band = rest - c * nbands;
     const size_t plane_words = (size_t)L * W;
-    int cx[kRChunk], cy[kRChunk];
+    uint32_t xn[kRChunk], xd[kRChunk], yn[kRChunk], yd[kRChunk];
 #pragma unroll
-    for (int j = 0; j < kRChunk; ++j) cx[j] = cy[j] = 0;
+    for (int j = 0; j < kRChunk; ++j) xn[j] = xd[j] = yn[j] = yd[j] = 0;
     if (c < 2) {
         const uint32_t* own = planes + (c ? plane_words : 0);
         for (uint32_t rr = 0; rr < rows; ++rr) {
@@ -145,80 +324,180 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
                     const uint4 py = reinterpret_cast<const uint4*>(pl)[(size_t)yr * Q + q];
                     const uint32_t m = (r & 1u) ? ((r - 1) >> 1) + par : (r >> 1);
                     const uint32_t* prow = pl + (size_t)y * W;
-                    int sx = 0, sy = 0;
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
                         const uint32_t o = pick(v, d);
-                        sy += pair_products(o, pick(py, d));
-                        sx += pair_products(o, shifted_word(prow, W, 4 * q + d, m));
+                        pair_counts(o, pick(py, d), yn[j], yd[j]);
+                        pair_counts(o, shifted_word(prow, W, 4 * q + d, m), xn[j], xd[j]);
                     }
-                    cx[j] += sx;
-                    cy[j] += sy;
                 }
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < kRChunk; ++j) {
-        const int sx = wave_sum_i32(cx[j]);
-        const int sy = wave_sum_i32(cy[j]);
+        const int64_t sx = wave_sum((int64_t)xn[j] - 2 * (int64_t)xd[j]);
+        const int64_t sy = wave_sum((int64_t)yn[j] - 2 * (int64_t)yd[j]);
         if ((threadIdx.x & 63) == 0 && j0 + j < nr) {
-            atomicAdd((unsigned long long*)&Cx[j0 + j], (unsigned long long)(int64_t)sx);
-            atomicAdd((unsigned long long*)&Cy[j0 + j], (unsigned long long)(int64_t)sy);
+            atomicAdd((unsigned long long*)&Cx[j0 + j], (unsigned long long)sx);
+            atomicAdd((unsigned long long*)&Cy[j0 + j], (unsigned long long)sy);
         }
     }
 }
 
-// Sampled sources (x = y = 0 mod 16): cell 0 of word a of plane 0, row 16 b.
-// Partners: along x (16 a + r, 16 b) is cell (8 a + r / 2) mod (L / 2) of
-// row 16 b in plane r & 1; along y (16 a, 16 b + r) is cell 0 of word a of
-// row 16 b + r in plane r & 1.  Block order puts the distance chunks of one
-// band of source rows next to each other so their partner rows are shared
-// in cache.
-__global__ __launch_bounds__(256) void corr_sampled_kernel(const uint32_t* __restrict__ planes, uint32_t L,
-                                                           uint32_t brows, uint32_t ablocks, uint32_t nchunks,
-                                                           const int32_t* __restrict__ rlist, int nr,
-                                                           int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
+// ---------------------------------------------------------------------------
+// a7, sampled sources.  Zs[b * W + a] = s(16 a, 16 b) as int8.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void zs_build_kernel(const uint32_t* __restrict__ plane0, uint32_t L,
+                                                       int8_t* __restrict__ zs)
 {
-    const uint32_t W = L >> 4;       // words per row = number of source columns
-    const uint32_t nb = L >> 4;      // number of source rows
-    const uint32_t half = L >> 1;
+    const uint32_t W = L >> 4;
+    const uint32_t nb = L >> 4;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * W) return;
+    const uint32_t b = g / W, a = g - b * W;
+    zs[g] = (int8_t)((int)(plane0[(size_t)16 * b * W + a] & 0xFu) - 1);
+}
+
+// Along x: one block per source row y = 16 b.  The row is unpacked into
+// one int8 per site (LDS, L bytes); thread t owns sources a = t, t + 256, ...
+constexpr int kXChunk = 16;
+
+// Cell of site (x, y) as a spin, read from the planes (used when a row of
+// int8 does not fit LDS).
+__device__ __forceinline__ int spin_at(const uint32_t* __restrict__ planes, size_t plane_words, uint32_t W, uint32_t x,
+                                       uint32_t y)
+{
+    const uint32_t c = (x + y) & 1u, i = x >> 1;
+    return (int)((planes[c * plane_words + (size_t)y * W + (i >> 3)] >> (4 * (i & 7))) & 0xFu) - 1;
+}
+
+// Persistent over source rows.  With USE_LDS the row is unpacked into L
+// int8 spins ordered by residue mod 16 (spin x at (x & 15) * (L / 16) +
+// (x >> 4)), so the 64 lanes of a wave, holding consecutive sources a, read
+// consecutive bytes; per-distance sums gather in LDS and leave with one
+// atomic per distance per workgroup.
+template <bool USE_LDS>
+__global__ __launch_bounds__(256) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                      const int32_t* __restrict__ rlist, int nr,
+                                                      int64_t* __restrict__ Cx)
+{
+    extern __shared__ int sx_lds[];                 // nr int32 sums, then the row
+    int* sums = sx_lds;
+    int8_t* srow = reinterpret_cast<int8_t*>(sx_lds + nr);
+    const uint32_t W = L >> 4;
+    const uint32_t P = L >> 4;                      // spins per residue class
     const size_t plane_words = (size_t)L * W;
-    const uint32_t ab = blockIdx.x % ablocks;
-    const uint32_t chunk = (blockIdx.x / ablocks) % nchunks;
-    const uint32_t band = blockIdx.x / (ablocks * nchunks);
-    const int j0 = (int)chunk * kRChunk;
-    const uint32_t a = ab * blockDim.x + threadIdx.x;
-    int cx[kRChunk], cy[kRChunk];
+    for (int k = threadIdx.x; k < nr; k += blockDim.x) sums[k] = 0;
+    for (uint32_t b = blockIdx.x; b < (L >> 4); b += gridDim.x) {
+        const uint32_t y = 16 * b;
+        if (USE_LDS) {
+            __syncthreads();
+            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+                const uint32_t c = idx >= W ? 1u : 0u;
+                const uint32_t wd = idx - c * W;
+                const uint32_t word = planes[c * plane_words + (size_t)y * W + wd];
+                const uint32_t par = (y + c) & 1u;              // x = 2 i + par
 #pragma unroll
-    for (int j = 0; j < kRChunk; ++j) cx[j] = cy[j] = 0;
-    if (a < W && band * brows < nb) {
-        for (uint32_t bb = 0; bb < brows; ++bb) {
-            const uint32_t y = 16u * (band * brows + bb);
-            const int src = (int)(planes[(size_t)y * W + a] & 0xFu) - 1;
-#pragma unroll
-            for (int j = 0; j < kRChunk; ++j) {
-                if (j0 + j < nr) {
-                    const uint32_t r = (uint32_t)rlist[j0 + j];
-                    const uint32_t* pl = planes + ((r & 1u) ? plane_words : 0);
-                    const uint32_t i = wrap(8u * a + (r >> 1), half);
-                    const int px = (int)((pl[(size_t)y * W + (i >> 3)] >> (4 * (i & 7))) & 0xFu) - 1;
-                    const uint32_t yr = wrap(y + r, L);
-                    const int py = (int)(pl[(size_t)yr * W + a] & 0xFu) - 1;
-                    cx[j] += src * px;
-                    cy[j] += src * py;
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t x = 2 * (8 * wd + k) + par;
+                    srow[(x & 15) * P + (x >> 4)] = (int8_t)((int)((word >> (4 * k)) & 0xFu) - 1);
                 }
+            }
+            __syncthreads();
+        }
+        for (int j0 = 0; j0 < nr; j0 += kXChunk) {
+            int acc[kXChunk];
+#pragma unroll
+            for (int k = 0; k < kXChunk; ++k) acc[k] = 0;
+            for (uint32_t a = threadIdx.x; a < W; a += blockDim.x) {
+                const int src = USE_LDS ? (int)srow[a] : spin_at(planes, plane_words, W, 16 * a, y);
+#pragma unroll
+                for (int k = 0; k < kXChunk; ++k) {
+                    if (j0 + k < nr) {
+                        const uint32_t x = wrap(16 * a + (uint32_t)rlist[j0 + k], L);
+                        acc[k] += src * (USE_LDS ? (int)srow[(x & 15) * P + (x >> 4)]
+                                                 : spin_at(planes, plane_words, W, x, y));
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kXChunk; ++k) {
+                const int s2 = wave_sum_i32(acc[k]);
+                if ((threadIdx.x & 63) == 0 && j0 + k < nr) atomicAdd(&sums[j0 + k], s2);
             }
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nr; k += blockDim.x)
+        if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
+}
+
+// Along y, target-row order: block (residue rho, list chunk, band of rows,
+// source chunk).  Target row y' = rho + 16 k pairs with source row
+// b = (y' - r) / 16 for every sampled r = rho (mod 16); the positions of
+// those r in the distance list are res_idx[res_off[rho] ..].  Thread t holds
+// the 4 targets (16 a, y') for a = a0 + 4 t .. + 3 as packed int8.
+constexpr int kYChunk = 32;
+constexpr int kYRows = 128;
+
+__global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                      const int8_t* __restrict__ zs,
+                                                      const int32_t* __restrict__ rlist,
+                                                      const int32_t* __restrict__ res_off,
+                                                      const int32_t* __restrict__ res_idx, uint32_t nchunk,
+                                                      uint32_t nband, uint32_t nachunk, int64_t* __restrict__ Cy)
+{
+    const uint32_t W = L >> 4;
+    uint32_t id = blockIdx.x;
+    const uint32_t ac = id % nachunk;
+    id /= nachunk;
+    const uint32_t band = id % nband;
+    id /= nband;
+    const uint32_t chunk = id % nchunk;
+    const uint32_t rho = id / nchunk;
+    const int p0 = res_off[rho] + (int)(chunk * kYChunk);
+    const int p1 = res_off[rho + 1];
+    if (p0 >= p1) return;
+    const uint32_t a0 = ac * 1024u + 4u * threadIdx.x;     // first of this thread's 4 columns
+    const bool live = a0 < W;                               // W is a multiple of 4
+    const size_t plane_words = (size_t)L * W;
+    int acc[kYChunk];
 #pragma unroll
-    for (int j = 0; j < kRChunk; ++j) {
-        const int sx = wave_sum_i32(cx[j]);
-        const int sy = wave_sum_i32(cy[j]);
-        if ((threadIdx.x & 63) == 0 && j0 + j < nr) {
-            atomicAdd((unsigned long long*)&Cx[j0 + j], (unsigned long long)(int64_t)sx);
-            atomicAdd((unsigned long long*)&Cy[j0 + j], (unsigned long long)(int64_t)sy);
+    for (int k = 0; k < kYChunk; ++k) acc[k] = 0;
+    const uint32_t nrows = L >> 4;                          // target rows per residue
+    for (uint32_t kk = 0; kk < kYRows; ++kk) {
+        const uint32_t krow = band * kYRows + kk;
+        if (krow >= nrows || !live) break;
+        const uint32_t yt = rho + 16 * krow;
+        const uint4 tw = *reinterpret_cast<const uint4*>(planes + (yt & 1u) * plane_words + (size_t)yt * W + a0);
+        // pack cell 0 of the 4 words as int8 (n - 1)
+        const uint32_t t0 = ((tw.x & 0xFu) - 1u) & 0xFFu, t1 = ((tw.y & 0xFu) - 1u) & 0xFFu;
+        const uint32_t t2 = ((tw.z & 0xFu) - 1u) & 0xFFu, t3 = ((tw.w & 0xFu) - 1u) & 0xFFu;
+        const int tp = (int)(t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
+#pragma unroll
+        for (int k = 0; k < kYChunk; ++k) {
+            const int p = p0 + k;
+            if (p < p1) {
+                const uint32_t r = (uint32_t)rlist[res_idx[p]];
+                const uint32_t ys = wrap(yt + L - r, L);    // source row 16 b
+                const int sp = *reinterpret_cast<const int*>(zs + (size_t)(ys >> 4) * W + a0);
+                acc[k] = __builtin_amdgcn_sdot4(sp, tp, acc[k], false);
+            }
         }
+    }
+    __shared__ int red[4][kYChunk];
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kYChunk; ++k) {
+        const int s2 = wave_sum_i32(acc[k]);
+        if ((threadIdx.x & 63) == 0) red[wave][k] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x < kYChunk && p0 + (int)threadIdx.x < p1) {
+        const int k = threadIdx.x;
+        const int64_t tot = (int64_t)red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        if (tot != 0) atomicAdd((unsigned long long*)&Cy[res_idx[p0 + k]], (unsigned long long)tot);
     }
 }
 
@@ -238,12 +517,31 @@ hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Persistent kernels use at most this many workgroups (a few per CU).
+constexpr uint32_t kMaxGrid = 2048;
+
 hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s)
 {
     const int64_t rows = pick_rows(g.L, 16);
     const int64_t threads = g.Q * (g.L / rows);
-    hipLaunchKernelGGL(bmq_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, g.plane(0), g.plane(1),
-                       g.L, rows, acc);
+    const uint32_t grid = (uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid);
+    hipLaunchKernelGGL(bmq_kernel, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
+                       (uint32_t)rows, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s)
+{
+    if (R < 0) return hipSuccess;
+    const uint32_t Q = (uint32_t)g.Q;
+    const uint32_t nstrips = (Q + kSW - 1) / kSW;
+    const uint32_t ntiles = nstrips * (uint32_t)(g.L / kTH);
+    const dim3 grid(std::min<uint32_t>(ntiles, 1024));
+    const uint32_t L = (uint32_t)g.L;
+    if (model == 0)
+        hipLaunchKernelGGL((corr_short_kernel<0>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
+    else
+        hipLaunchKernelGGL((corr_short_kernel<1>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
     return hipGetLastError();
 }
 
@@ -258,16 +556,44 @@ hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t*
     return hipGetLastError();
 }
 
-hipError_t launch_corr_sampled(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy, hipStream_t s)
+hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
-    if (nr <= 0) return hipSuccess;
-    const int64_t nb = g.L / 16;
-    const int64_t brows = pick_rows(nb, 8);
-    const uint32_t ablocks = (uint32_t)((g.W + 255) / 256);
-    const uint32_t chunks = (uint32_t)((nr + kRChunk - 1) / kRChunk);
-    const int64_t blocks = (int64_t)ablocks * chunks * (nb / brows);
-    hipLaunchKernelGGL(corr_sampled_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, g.plane0, (uint32_t)g.L,
-                       (uint32_t)brows, ablocks, chunks, r_dev, nr, Cx, Cy);
+    if (a.nr <= 0) return hipSuccess;
+    const uint32_t L = (uint32_t)g.L, W = (uint32_t)g.W, nb = L / 16;
+    hipLaunchKernelGGL(zs_build_kernel, dim3((nb * W + 255) / 256), dim3(256), 0, s, g.plane0, L, a.zs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // along x: LDS holds the distance sums of a launch (<= 8192 distances
+    // each) and, when it fits in the 160 KiB of a workgroup, the int8 row
+    const int kMaxR = 8192;
+    const uint32_t gx = std::min<uint32_t>(nb, 1024);
+    for (int j0 = 0; j0 < a.nr; j0 += kMaxR) {
+        const int nr = std::min(kMaxR, a.nr - j0);
+        const size_t lds_sums = (size_t)nr * 4;
+        const bool use_lds = lds_sums + L <= 160u * 1024u;
+        const size_t lds = lds_sums + (use_lds ? L : 0);
+        static size_t attr_bytes[2] = {0, 0};
+        const void* fn = use_lds ? (const void*)corr_sx_kernel<true> : (const void*)corr_sx_kernel<false>;
+        if (lds > 64u * 1024u && attr_bytes[use_lds] < lds) {
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            attr_bytes[use_lds] = lds;
+        }
+        if (use_lds)
+            hipLaunchKernelGGL(corr_sx_kernel<true>, dim3(gx), dim3(256), lds, s, g.plane0, L, a.r + j0, nr,
+                               a.Cx + j0);
+        else
+            hipLaunchKernelGGL(corr_sx_kernel<false>, dim3(gx), dim3(256), lds, s, g.plane0, L, a.r + j0, nr,
+                               a.Cx + j0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t nchunk = (uint32_t)((a.max_per_residue + kYChunk - 1) / kYChunk);
+    const uint32_t nband = (nb + kYRows - 1) / kYRows;
+    const uint32_t nachunk = (W + 1023) / 1024;
+    if (nchunk == 0) return hipSuccess;
+    hipLaunchKernelGGL(corr_sy_kernel, dim3(16u * nchunk * nband * nachunk), dim3(256), 0, s, g.plane0, L, a.zs, a.r,
+                       a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
     return hipGetLastError();
 }
 

@@ -1,27 +1,11 @@
-// Initial state and half-sweep kernels for gfx950 (rows a1, a3, a4).
-//
-// A half-sweep updates every cell of colour c (plane P_c) from its four
-// neighbours, which all live in the other plane P_{1-c} (checkerboard
-// decomposition, section 3.1):
-//   vertical neighbours  : same in-plane index i, rows y - 1 and y + 1;
-//   horizontal neighbours: row y, indices {i - 1, i} when (y + c) is even,
-//                          {i, i + 1} when it is odd (periodic in i and y).
-// Each thread owns one 16-byte column vector (32 cells) and walks down a band
-// of rows, keeping the other plane's rows y - 1, y, y + 1 in registers, so
-// every row of both planes is read once per band (plus one halo row above
-// and below the band) and every row of P_c is written once.
+// Initial state and the one-lattice half-sweep kernel for gfx950 (rows a1,
+// a3, a4); the per-thread update is in sweep_device.h.
 #include "internal.h"
+#include "sweep_device.h"
 
 namespace mcl {
 namespace {
 
-__device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
-__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
-
-__device__ __forceinline__ uint32_t pick(const uint4& v, int d)
-{
-    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
-}
 
 // ---------------------------------------------------------------------------
 // a1: initial state.  One thread per 32-bit word (8 cells) of one plane.
@@ -51,7 +35,7 @@ __global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes
             const int64_t x = 2 * i + ((y + color) & 1);
             const uint64_t n = (uint64_t)(y * L + x);
             const uint64_t blk = n >> 2;
-            const Philox4 o = philox4x32_10(lo32(blk), hi32(blk), 0u, 4u, k0, k1);
+            const Philox4 o = philox4x32_10(dev::lo32(blk), dev::hi32(blk), 0u, 4u, k0, k1);
             const uint32_t sel = (uint32_t)(n & 3);
             const uint32_t w = sel == 0 ? o.v0 : sel == 1 ? o.v1 : sel == 2 ? o.v2 : o.v3;
             if (model == 0)
@@ -64,246 +48,20 @@ __global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes
     planes[g] = word;
 }
 
-// ---------------------------------------------------------------------------
-// Acceptance bits of the 32 cells of one 16-byte vector.  Cell j (0..7) of
-// word d (0..3) is in-colour site kv + 8d + j; its accept draw is output
-// word j & 3 of Philox block (kv >> 2) + 2d + (j >> 2).  Returns, for each
-// threshold T, a 32-bit mask whose bit 4j + d is [u < T]: the "transposed"
-// order lets each mask be built with one carry-chain add per cell
-// (acc = acc + acc + carry) and lets word d read its cells' bits at nibble
-// bit 0 as (mask >> d) & 0x11111111.
-// ---------------------------------------------------------------------------
-template <bool HI0>
-__device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t color, uint32_t k0, uint32_t k1,
-                                             uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
-{
-    uint32_t a4 = 0, a8 = 0;
-#pragma unroll
-    for (int h = 1; h >= 0; --h) {
-        Philox4 P[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
-        }
-#pragma unroll
-        for (int jj = 3; jj >= 0; --jj)
-#pragma unroll
-            for (int d = 3; d >= 0; --d) {
-                const uint32_t u = philox_word(P[d], jj);
-                a4 = shift_in_lt(a4, u, T4);
-                a8 = shift_in_lt(a8, u, T8);
-            }
-    }
-    m4 = a4;
-    m8 = a8;
-}
-
-// Horizontal neighbour word of word d of vector `mid`: cells i - 1 (even
-// row parity) or i + 1 (odd) of the other plane, with `halo` the adjacent
-// word outside the vector on that side.
-__device__ __forceinline__ uint32_t horizontal(const uint4& mid, int d, uint32_t halo, bool odd)
-{
-    const uint32_t w = pick(mid, d);
-    if (odd) return funnel(d < 3 ? pick(mid, d + 1) : halo, w, 4);
-    return funnel(w, d > 0 ? pick(mid, d - 1) : halo, 28);
-}
-
-// ---------------------------------------------------------------------------
-// a3: Ising vector update (32 cells).  Cells hold n in {0, 2}; n ^ src is 2
-// for a misaligned neighbour, so half the per-nibble sum of the four xors is
-// the number m of misaligned neighbours.  The flip rule of section 3.2
-// (always with at most two aligned neighbours, with probability e^{-4 beta}
-// with three, e^{-8 beta} with four) is: flip iff m + [u < T4] + [u < T8]
-// >= 2, since T8 <= T4.  Adding 6 moves that test to nibble bit 3.
-// ---------------------------------------------------------------------------
-template <bool HI0>
-__device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
-                                           uint32_t halo, bool odd, uint64_t blk0, uint32_t t, uint32_t color,
-                                           uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8)
-{
-    uint32_t m4, m8;
-    accept_masks<HI0>(blk0, t, color, k0, k1, T4, T8, m4, m8);
-    uint32_t res[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const uint32_t s = pick(src, d);
-        const uint32_t hs = horizontal(mid, d, halo, odd);
-        const uint32_t m = ((pick(up, d) ^ s) + (pick(dn, d) ^ s) + (pick(mid, d) ^ s) + (hs ^ s)) >> 1;
-        const uint32_t lvl = ((m4 >> d) & 0x11111111u) + ((m8 >> d) & 0x11111111u);
-        const uint32_t f = (m + lvl + 0x66666666u) & 0x88888888u;
-        res[d] = s ^ (f >> 2);
-    }
-    return make_uint4(res[0], res[1], res[2], res[3]);
-}
-
-// ---------------------------------------------------------------------------
-// a4: Blume-Capel vector update (32 cells).  Per cell: the proposal
-// s' = ((n + 1 + b) mod 3) - 1 (n = s + 1, b the proposal bit), then a table
-// lookup on (n, b, sum of neighbour cells) gives the threshold and whether
-// dE <= 0; accept = always | (u < thr), as a 33-bit borrow
-// (0:u) - (always:thr).  Word-level: n + 1 + b and its reduction mod 3 are
-// nibble-parallel; the accept bits gate the new values in with a bit select.
-// ---------------------------------------------------------------------------
-// Spread the low 8 bits of x to bit 0 of the 8 nibbles.
-__device__ __forceinline__ uint32_t spread8(uint32_t x)
-{
-    x &= 0xFFu;
-    x = (x | (x << 12)) & 0x000F000Fu;
-    x = (x | (x << 6)) & 0x03030303u;
-    x = (x | (x << 3)) & 0x11111111u;
-    return x;
-}
-
-template <bool HI0>
-__device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
-                                        uint32_t halo, bool odd, uint64_t blk0, uint32_t pbits, uint32_t t,
-                                        uint32_t color, uint32_t k0, uint32_t k1, const uint2* __restrict__ tab)
-{
-    uint32_t key[4], sum[4], nxt[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const uint32_t s = pick(src, d);
-        const uint32_t b = spread8(pbits >> (8 * d));
-        sum[d] = pick(up, d) + pick(dn, d) + pick(mid, d) + horizontal(mid, d, halo, odd);
-        key[d] = s + s + b;                                   // n * 2 + b, at most 5 per nibble
-        const uint32_t v = s + 0x11111111u + b;               // n + 1 + b in 1..4
-        const uint32_t ge3 = ((v + 0x55555555u) & 0x88888888u) >> 3;
-        nxt[d] = v - (ge3 | (ge3 << 1));                      // mod 3
-    }
-    uint32_t acc = 0;
-#pragma unroll
-    for (int h = 1; h >= 0; --h) {
-        Philox4 P[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
-        }
-#pragma unroll
-        for (int jj = 3; jj >= 0; --jj)
-#pragma unroll
-            for (int d = 3; d >= 0; --d) {
-                const int j = 4 * h + jj;
-                const uint32_t kj = (key[d] >> (4 * j)) & 0xFu;
-                const uint32_t sj = (sum[d] >> (4 * j)) & 0xFu;
-                uint32_t idx = kj * 16u + sj;
-                idx = idx < 95u ? idx : 95u;
-                const uint2 e = tab[idx];
-                const uint32_t u = philox_word(P[d], jj);
-                const uint64_t lhs = (uint64_t)u;
-                const uint64_t rhs = ((uint64_t)e.y << 32) | e.x;
-                acc = acc + acc + (uint32_t)(lhs < rhs);
-            }
-    }
-    uint32_t res[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const uint32_t s = pick(src, d);
-        const uint32_t a = (acc >> d) & 0x11111111u;
-        const uint32_t mask = (a << 4) - a;                   // 0xF in accepted nibbles
-        res[d] = (s & ~mask) | (nxt[d] & mask);
-    }
-    return make_uint4(res[0], res[1], res[2], res[3]);
-}
-
-// Blume-Capel table in LDS, 96 entries indexed (n * 2 + b) * 16 + cell-sum:
-// x = threshold, y = 1 when dE <= 0 (always accept).  Unused slots (sum > 8,
-// n > 2) never accept.
-struct BCLds {
-    uint2 e[96];
-};
-
-__device__ __forceinline__ void load_bc_table(BCLds& lds, const BCTable& tbl)
-{
-    for (uint32_t i = threadIdx.x; i < 96u; i += blockDim.x) {
-        const uint32_t key = i >> 4, sj = i & 15u;
-        uint2 v = make_uint2(0u, 0u);
-        if (key < 6u && sj < 9u) {
-            const uint32_t n = key >> 1, b = key & 1u;
-            const uint32_t idx = (n * 2u + b) * 9u + sj;
-            v = make_uint2(tbl.thr[idx], tbl.always[idx] ? 1u : 0u);
-        }
-        lds.e[i] = v;
-    }
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Half-sweep: one thread per 16-byte column vector, walking `rows` rows
-// (even, starting at an even row).  The colour is a template parameter, so
-// the parity of y + c, which picks the horizontal neighbours, is known at
-// compile time for the two rows of each unrolled pair.
-// ---------------------------------------------------------------------------
-struct RowState {
-    const uint4* pcur;      // other plane, row y, this column
-    uint4* pown;            // own plane, row y, this column
-    const uint32_t* hrow;   // other plane, row y, word 0
-    uint64_t blk;           // accept block of the vector's cell 0
-    uint64_t kv;            // in-colour index of the vector's cell 0
-    uint4 up, mid;
-};
-
-template <int MODEL, bool HI0, bool ODD>
-__device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__ oth_col0, uint32_t y, uint32_t L,
-                                         uint32_t Q, uint32_t W, uint32_t hwl, uint32_t hwr, uint32_t color,
-                                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8,
-                                         const uint2* tab)
-{
-    const uint4* pdn = (y + 1 == L) ? oth_col0 : st.pcur + Q;
-    const uint4 dn = *pdn;
-    const uint4 src = *st.pown;
-    const uint32_t halo = st.hrow[ODD ? hwr : hwl];
-    uint4 res;
-    if (MODEL == 0) {
-        res = ising_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, t, color, k0, k1, T4, T8);
-    } else {
-        const uint64_t pb = st.kv >> 7;
-        const Philox4 p = philox4x32_10(lo32(pb), HI0 ? 0u : hi32(pb), t, 2u + color, k0, k1);
-        const uint32_t pbits = philox_word(p, (int)((st.kv >> 5) & 3));
-        res = bc_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, pbits, t, color, k0, k1, tab);
-    }
-    *st.pown = res;
-    st.up = st.mid;
-    st.mid = dn;
-    st.pcur += Q;
-    st.pown += Q;
-    st.hrow += W;
-    st.blk += L >> 3;
-    st.kv += L >> 1;
-}
-
 template <int MODEL, bool HI0, int COLOR>
 __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
                                                          uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
                                                          uint32_t k1, uint32_t T4, uint32_t T8, BCTable tbl)
 {
-    __shared__ BCLds s_tab;
-    if (MODEL == 1) load_bc_table(s_tab, tbl);
+    __shared__ dev::BCLds s_tab;
+    if (MODEL == 1) dev::load_bc_table(s_tab, tbl);
     const uint32_t Q = L >> 6;
-    const uint32_t W = L >> 4;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t q = g % Q;
     const uint32_t band = g / Q;
     const uint32_t y0 = band * rows;
     if (y0 >= L) return;
-    const uint4* __restrict__ oth4 = reinterpret_cast<const uint4*>(oth) + q;
-    RowState st;
-    st.pcur = oth4 + (size_t)y0 * Q;
-    st.pown = reinterpret_cast<uint4*>(own) + (size_t)y0 * Q + q;
-    st.hrow = oth + (size_t)y0 * W;
-    st.blk = ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2;
-    st.kv = (uint64_t)y0 * (L >> 1) + 32u * q;
-    st.up = *(oth4 + (size_t)(y0 == 0 ? L - 1 : y0 - 1) * Q);
-    st.mid = *st.pcur;
-    const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;         // word left of the vector
-    const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;     // word right of the vector
-    for (uint32_t r = 0; r < rows; r += 2) {
-        // even row y: parity of y + c is c; odd row: 1 - c
-        row_step<MODEL, HI0, COLOR == 1>(st, oth4, y0 + r, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8, s_tab.e);
-        row_step<MODEL, HI0, COLOR == 0>(st, oth4, y0 + r + 1, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8,
-                                         s_tab.e);
-    }
+    dev::band_update<MODEL, HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, T4, T8, s_tab.e);
 }
 
 int64_t band_rows(int64_t L)

@@ -60,7 +60,9 @@ def test_library_does_not_link_the_oracle(mcl):
 def test_query_bytes(mcl):
     assert mcl.query_bytes(mcl.ISING, 256) >= 256 * 256 // 2
     assert mcl.query_bytes(mcl.ISING, 2**17) >= 2**33
-    assert mcl.query_bytes(mcl.BC, 2**16) < 2**31 + 2**22
+    for L in (64, 256, 2**16, 2**17):
+        # two 4-bit planes, then scratch: (L/16)^2 int8 sampled sources + O(L) sums
+        assert L * L // 2 <= mcl.query_bytes(mcl.BC, L) <= L * L // 2 + L * L // 256 + 64 * L + 8192
     with pytest.raises(mcl.MclError):
         mcl.query_bytes(mcl.ISING, 96 + 1)
     with pytest.raises(mcl.MclError):
@@ -115,3 +117,23 @@ def test_argument_errors_before_device_work(mcl):
                               (ctypes.c_uint8 * 54)(), 54) == -4
     for code in range(0, -12, -1):
         assert lib.mcl_strerror(code)
+
+
+def test_group_tuning_roundtrip_and_validation(mcl):
+    from paper_2502_18624_amd._lib import GroupTuning
+    lib = mcl.lib()
+    saved = GroupTuning()
+    assert lib.mcl_group_tuning_get(ctypes.byref(saved)) == 0
+    assert all(r in (8, 16, 32, 64) for r in saved.rows_log2L)
+    t = GroupTuning()
+    ctypes.memmove(ctypes.byref(t), ctypes.byref(saved), ctypes.sizeof(t))
+    t.rows_log2L[10] = 12                     # not a supported band height
+    assert lib.mcl_group_tuning_set(ctypes.byref(t)) == -9
+    t.rows_log2L[10] = 64
+    t.use_graph = 1
+    assert lib.mcl_group_tuning_set(ctypes.byref(t)) == 0
+    back = GroupTuning()
+    lib.mcl_group_tuning_get(ctypes.byref(back))
+    assert back.rows_log2L[10] == 64 and back.use_graph == 1
+    assert lib.mcl_group_tuning_set(ctypes.byref(saved)) == 0
+    assert lib.group_sweep(None, 0, None, None, None) == 0     # empty group is a no-op

@@ -157,6 +157,58 @@ def test_measure_structured_states(mcl):
         assert np.array_equal(m["Cx"], abs(val) * m["nsrc"]) and np.array_equal(m["Cy"], abs(val) * m["nsrc"])
 
 
+def _tuning(mcl, rows=None, graph=0, largest=1):
+    from paper_2502_18624_amd._lib import GroupTuning
+    import ctypes
+    t = GroupTuning()
+    mcl.lib().mcl_group_tuning_get(ctypes.byref(t))
+    if rows is not None:
+        for k in range(21):
+            t.rows_log2L[k] = rows
+    t.use_graph = graph
+    t.largest_first = largest
+    assert mcl.lib().mcl_group_tuning_set(ctypes.byref(t)) == 0
+    return t
+
+
+@pytest.mark.parametrize("rows,graph,largest", [(8, 0, 1), (16, 1, 0), (32, 1, 1), (64, 0, 0)])
+def test_group_sweep_tunings_are_bit_identical(mcl, rows, graph, largest):
+    """Every tuning of the batched path gives the plain path's lattices: the
+    draws are keyed by the logical site, never by the launch shape."""
+    print("group tuning", rows, graph, largest, flush=True)
+    import ctypes
+    from paper_2502_18624_amd._lib import GroupTuning
+    saved = GroupTuning()
+    mcl.lib().mcl_group_tuning_get(ctypes.byref(saved))
+    try:
+        _tuning(mcl, rows, graph, largest)
+        rng = np.random.default_rng(rows + 10 * graph + 100 * largest)
+        specs = []
+        for i in range(7):
+            model = int(rng.integers(0, 2))
+            L = int(rng.choice([64, 128, 192, 256, 512]))
+            n = int(rng.integers(0, 5))                     # n = 0: left untouched
+            specs.append((model, L, 3000 + i, n, float(rng.uniform(0.5, 1.5)) * BETA_C,
+                          float(rng.choice([0.0, 0.5, 1.0]))))
+        lats = [mcl.Lattice(m, L, sd) for (m, L, sd, _, _, _) in specs]
+        for rep in range(2):                                 # second call reuses a cached graph
+            mcl.group_sweep(lats, [sp[3] for sp in specs], [sp[4] for sp in specs], [sp[5] for sp in specs])
+        for lat, (m, L, sd, n, b, D) in zip(lats, specs):
+            assert lat.t == 2 * n
+            want = _oracle_run(m, L, sd, 0, 2 * n, b, D)
+            assert np.array_equal(lat.read(), want), (m, L, n)
+    finally:
+        mcl.lib().mcl_group_tuning_set(ctypes.byref(saved))
+
+
+def test_group_sweep_rejects_mixed_streams(mcl):
+    import torch
+    a = mcl.Lattice(0, 64, 1)
+    b = mcl.Lattice(0, 64, 2, stream=torch.cuda.Stream())
+    with pytest.raises(mcl.MclError):
+        mcl.group_sweep([a, b], [1, 1], [0.5, 0.5])
+
+
 def test_group_sweep_equals_plain(mcl):
     rng = np.random.default_rng(3)
     specs = []
