@@ -95,6 +95,133 @@ def attainable_copy():
     return max(vals) if vals else None
 
 
+def replica_set(n=512, seed=3):
+    """Batched workload: n replicas alternating Ising / Blume-Capel, L uniform
+    over {512 ... 8192}, T ~ U[0.5, 1.5] T_c, D in {0, 0.5, 1} (Blume-Capel),
+    replica i seeded 2000 + i; parameters from numpy default_rng(seed)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        model = i % 2
+        L = int(rng.choice([512, 1024, 2048, 4096, 8192]))
+        T = float(rng.uniform(0.5, 1.5)) / BETA_C
+        D = float(rng.choice([0.0, 0.5, 1.0])) if model == 1 else 0.0
+        out.append((model, L, 2000 + i, 1.0 / T, D))
+    return out
+
+
+def run_blume_capel(args):
+    """Blume-Capel quench, L = 2^16, T = 1.4, D = 1, random start; B/M/Q and
+    protocol C(r,t) at t = 2^k."""
+    import torch
+
+    import paper_2502_18624_amd as mcl
+    L, n = 2 ** 16, args.bc_sweeps
+    stream = torch.cuda.current_stream()
+    lat = mcl.Lattice(mcl.BC, L, 1003, stream=stream)
+    lat.sweep(2, 1 / 1.4, 1.0)                       # warm-up, then restart the quench
+    torch.cuda.synchronize()
+    mem = lat.mem
+    lat.free()
+    lat = mcl.Lattice(mcl.BC, L, 1003, stream=stream, mem=mem)
+    torch.cuda.synchronize()
+    marks = [2 ** k for k in range(20) if 2 ** k <= n]
+    ev, done, t_meas = [], 0, 0.0
+    wall0 = time.perf_counter()
+    last = None
+    for m in marks + [n]:
+        if m > done:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.sweep(m - done, 1 / 1.4, 1.0)
+            b.record(stream)
+            ev.append((a, b, m - done))
+            done = m
+        if m in marks and (last is None or last != m):
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            out = lat.measure(mcl.CORR_PROTOCOL)
+            t_meas += time.perf_counter() - tm
+            last = m
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    upd = float(L) * L * n
+    res = {"workload": "Blume-Capel quench, L=2^16, T=1.4, D=1.0, random start, %d sweeps, protocol C(r,t) and "
+                       "B/M/Q at t=2^k" % n,
+           "updates_per_ns": round(upd / (wall * 1e9), 2),
+           "sweep_only_updates_per_ns": round(upd / (sweep_ms * 1e6), 2),
+           "avg_half_sweep_ms": round(sweep_ms / (2 * n), 4),
+           "hbm_frac": round(3.0 * L * L / 4.0 / (sweep_ms / (2 * n) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "measure_share": round(t_meas / wall, 4),
+           "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"]},
+           "paper_context_updates_per_ns": 941}
+    lat.free()
+    return res
+
+
+def run_batched(args):
+    """Batched vs plain on the same replica set: group_sweep (autotuned) and
+    one lattice per launch, sweep by sweep."""
+    import torch
+
+    import paper_2502_18624_amd as mcl
+    from paper_2502_18624_amd.autotune import autotune_group
+    specs = replica_set(args.replicas)
+    n = args.batched_sweeps
+    tune = autotune_group([(m, L) for (m, L, _, _, _) in specs], sweeps_per_call=8, reps=1)
+    lats = [mcl.Lattice(m, L, sd) for (m, L, sd, _, _) in specs]
+    betas = [b for (_, _, _, b, _) in specs]
+    Ds = [d for (_, _, _, _, d) in specs]
+    upd = float(sum(L * L for (_, L, _, _, _) in specs)) * n
+    mcl.group_sweep(lats, [1] * len(lats), betas, Ds)           # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mcl.group_sweep(lats, [n] * len(lats), betas, Ds)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k in range(n):
+        for lat, b, d in zip(lats, betas, Ds):
+            lat.sweep(1, b, d)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for lat in lats:
+        lat.free()
+    return {"workload": "%d replicas (alternating Ising / Blume-Capel), L in {512..8192}, T ~ U[0.5,1.5] T_c, "
+                        "D in {0,0.5,1}, %d sweeps each" % (len(specs), n),
+            "spins": int(sum(L * L for (_, L, _, _, _) in specs)),
+            "batched_updates_per_ns": round(upd / (t_batched * 1e9), 2),
+            "plain_updates_per_ns": round(upd / (t_plain * 1e9), 2),
+            "batched_over_plain": round(t_plain / t_batched, 3),
+            "tuning": {k: v for k, v in tune.items() if k != "rows_log2L"} | {
+                "rows_by_L": {str(2 ** k): tune["rows_log2L"][k] for k in range(9, 14)}}}
+
+
+def run_serving(args):
+    """Poisson stream of quench jobs through the continuous-batching server:
+    the first `serve_jobs` arrivals at 200 jobs/s (offered load far above one
+    GPU), then a trace at about 70% of the measured batched rate."""
+    from paper_2502_18624_amd.serve import Server, poisson_trace
+    out = {}
+    mean_work = None
+    for name, rate in (("poisson_200_per_s", 200.0), ("sustainable", None)):
+        if rate is None:
+            cap = out["poisson_200_per_s"]["updates_per_ns"] * 1e9
+            rate = 0.7 * cap / mean_work
+        jobs = poisson_trace(args.serve_jobs, rate_per_s=rate, seed=4)
+        mean_work = sum(j.updates for j in jobs) / len(jobs)
+        srv = Server(hbm_budget=250e9, tick_seconds=0.02)
+        st = srv.run_trace(jobs)
+        st["rate_per_s"] = round(rate, 3)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    out["workload"] = ("Poisson quench jobs (Ising/Blume-Capel 50/50), L = 64 round(2^U[10,15]/64), sweeps = "
+                       "round(10^U[2,4]), T ~ U[0.5,1.5] T_c, D in {0,0.5,1}, admitted by footprint up to 250 GB; "
+                       "first %d arrivals" % args.serve_jobs)
+    return out
+
+
 def run(args):
     import torch
 
@@ -197,12 +324,25 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", type=int, default=2 ** 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
+    ap.add_argument("--bc-sweeps", type=int, default=2000)
+    ap.add_argument("--replicas", type=int, default=512)
+    ap.add_argument("--batched-sweeps", type=int, default=100)
+    ap.add_argument("--serve-jobs", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     res = run(args)
+    if not args.no_extras:
+        log("bench: Blume-Capel L=2^16")
+        res["blume_capel"] = run_blume_capel(args)
+        log("bench: batched vs plain")
+        res["batched"] = run_batched(args)
+        res["batched_over_plain"] = res["batched"]["batched_over_plain"]
+        log("bench: serving")
+        res["serving"] = run_serving(args)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         res["cpu_baseline"] = cpu_baseline()

@@ -376,9 +376,10 @@ __device__ __forceinline__ int spin_at(const uint32_t* __restrict__ planes, size
 // int8 spins ordered by residue mod 16 (spin x at (x & 15) * (L / 16) +
 // (x >> 4)), so the 64 lanes of a wave, holding consecutive sources a, read
 // consecutive bytes; per-distance sums gather in LDS and leave with one
-// atomic per distance per workgroup.
+// atomic per distance per workgroup.  The row takes most of a CU's LDS, so
+// a workgroup is 1024 threads (16 waves) to hide LDS latency.
 template <bool USE_LDS>
-__global__ __launch_bounds__(256) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+__global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
                                                       const int32_t* __restrict__ rlist, int nr,
                                                       int64_t* __restrict__ Cx)
 {
@@ -566,7 +567,7 @@ hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t 
     // along x: LDS holds the distance sums of a launch (<= 8192 distances
     // each) and, when it fits in the 160 KiB of a workgroup, the int8 row
     const int kMaxR = 8192;
-    const uint32_t gx = std::min<uint32_t>(nb, 1024);
+    const uint32_t gx = std::min<uint32_t>(nb, 512);
     for (int j0 = 0; j0 < a.nr; j0 += kMaxR) {
         const int nr = std::min(kMaxR, a.nr - j0);
         const size_t lds_sums = (size_t)nr * 4;
@@ -580,10 +581,10 @@ hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t 
             attr_bytes[use_lds] = lds;
         }
         if (use_lds)
-            hipLaunchKernelGGL(corr_sx_kernel<true>, dim3(gx), dim3(256), lds, s, g.plane0, L, a.r + j0, nr,
+            hipLaunchKernelGGL(corr_sx_kernel<true>, dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
                                a.Cx + j0);
         else
-            hipLaunchKernelGGL(corr_sx_kernel<false>, dim3(gx), dim3(256), lds, s, g.plane0, L, a.r + j0, nr,
+            hipLaunchKernelGGL(corr_sx_kernel<false>, dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
                                a.Cx + j0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
