@@ -28,7 +28,8 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 PHILOX_OPS_PER_BLOCK = 40
 PHILOX_PEAK_GBLOCKS = VALU_LANE_OPS / PHILOX_OPS_PER_BLOCK / 1e9
 METRIC = "lattice updates/ns on 1 MI355X (Ising L=2^17); % HBM peak; batched vs plain"
-SWEEP_SOURCES = ["paper_2502_18624_amd/csrc/sweep.hip", "paper_2502_18624_amd/csrc/common.h"]
+SWEEP_SOURCES = ["paper_2502_18624_amd/csrc/sweep.hip", "paper_2502_18624_amd/csrc/sweep_device.h",
+                 "paper_2502_18624_amd/csrc/common.h"]
 
 
 def log(*a):

@@ -76,6 +76,11 @@ def lib():
         L.ora_corr.argtypes = [ctypes.c_void_p, i64, ctypes.c_int, P(i32), ctypes.c_int,
                                P(i64), P(i64), P(i64)]
         L.ora_sd_hist.argtypes = [ctypes.c_void_p, i64, P(i64)]
+        L.ora_init_window.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_int, i64, u64, ctypes.c_int]
+        L.ora_init_window.restype = ctypes.c_int
+        L.ora_sweep_window.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_int, i64, u64, i64, i64,
+                                       ctypes.c_double, ctypes.c_double]
+        L.ora_sweep_window.restype = ctypes.c_int
         L.ora_series.argtypes = [ctypes.c_void_p, ctypes.c_int, i64, u64, i64, i64,
                                  ctypes.c_double, ctypes.c_double, P(i64), P(i64), P(i64)]
         L.ora_series.restype = ctypes.c_int
@@ -207,6 +212,20 @@ def sd_hist(s):
     h = np.zeros(9, dtype=np.int64)
     lib().ora_sd_hist(s.ctypes.data, s.shape[0], _ptr(h, ctypes.c_int64))
     return h
+
+
+def window_run(model, L, seed, x0, y0, P, n, beta, D=0.0, init_state=INIT_RANDOM, t0=0):
+    """Patch of P x P sites at (x0, y0) of an L x L lattice after n sweeps
+    from its initial state; rows and columns at least 2n from the patch edge
+    are exact (light cone)."""
+    p = np.empty((P, P), dtype=np.int8)
+    rc = lib().ora_init_window(p.ctypes.data, P, x0, y0, model, L, seed, init_state)
+    if rc:
+        raise ValueError("ora_init_window failed (%d)" % rc)
+    rc = lib().ora_sweep_window(p.ctypes.data, P, x0, y0, model, L, seed, t0, n, float(beta), float(D))
+    if rc:
+        raise ValueError("ora_sweep_window failed (%d)" % rc)
+    return p
 
 
 def series(s, model, seed, t0, n, beta, D=0.0):

@@ -457,3 +457,82 @@ int ora_series(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0, int64
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Light-cone windows (see oracle.h).  The rule is the one of update_site,  */
+/* evaluated at global coordinates; only the bookkeeping of which sites are */
+/* present differs.                                                         */
+/* ------------------------------------------------------------------------ */
+static int init_value(int model, uint64_t seed, int init_state, uint64_t n)
+{
+    if (init_state == ORA_INIT_UP) return 1;
+    if (init_state == ORA_INIT_DOWN) return -1;
+    if (init_state == ORA_INIT_ZERO) return 0;
+    {
+        uint32_t w = ora_init_draw(seed, n);
+        if (model == ORA_ISING) return (w < 0x80000000u) ? 1 : -1;
+        return (int)(((uint64_t)w * 3u) >> 32) - 1;
+    }
+}
+
+int ora_init_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model, int64_t L, uint64_t seed,
+                    int init_state)
+{
+    int64_t i, j;
+    if (L < 3 || P < 3 || P > L) return -1;
+    if (model != ORA_ISING && model != ORA_BC) return -1;
+    if (init_state == ORA_INIT_ZERO && model == ORA_ISING) return -1;
+    for (j = 0; j < P; j++)
+        for (i = 0; i < P; i++) {
+            int64_t x = ((x0 + i) % L + L) % L, y = ((y0 + j) % L + L) % L;
+            patch[j * P + i] = (int8_t)init_value(model, seed, init_state, (uint64_t)(y * L + x));
+        }
+    return 0;
+}
+
+int ora_sweep_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model, int64_t L, uint64_t seed,
+                     int64_t t0, int64_t n, double beta, double D)
+{
+    struct sweep_tables tb;
+    int64_t it;
+    if (L < 3 || P < 3 || P > L || (L % 2) != 0) return -1;
+    if (model != ORA_ISING && model != ORA_BC) return -1;
+    if (beta != beta || beta < 0.0) return -2;
+    if (D != D) return -3;
+    if (t0 < 0 || n < 0 || t0 + n > 4294967296LL) return -4;
+    build_tables(&tb, model, beta, D);
+    for (it = 0; it < n; it++) {
+        uint32_t t = (uint32_t)(t0 + it);
+        int color;
+        for (color = 0; color < 2; color++) {
+            int64_t i, j;
+            for (j = 1; j < P - 1; j++)
+                for (i = 1; i < P - 1; i++) {
+                    int64_t x = ((x0 + i) % L + L) % L, y = ((y0 + j) % L + L) % L;
+                    int8_t* c = &patch[j * P + i];
+                    int sv = *c, nb[4], h, s2;
+                    uint64_t k;
+                    if (((x + y) & 1) != color) continue;
+                    k = (uint64_t)(y * L + x) >> 1;
+                    nb[0] = patch[j * P + i + 1];
+                    nb[1] = patch[j * P + i - 1];
+                    nb[2] = patch[(j + 1) * P + i];
+                    nb[3] = patch[(j - 1) * P + i];
+                    h = nb[0] + nb[1] + nb[2] + nb[3];
+                    if (model == ORA_ISING) {
+                        int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
+                        int flip = aligned <= 2;
+                        if (!flip) flip = ora_accept_draw(seed, t, color, k) < (aligned == 3 ? tb.T4 : tb.T8);
+                        if (flip) *c = (int8_t)(-sv);
+                    } else {
+                        int b = ora_proposal_bit(seed, t, color, k);
+                        int accept = tb.always[sv + 1][b][h + 4];
+                        s2 = bc_propose(sv, b);
+                        if (!accept) accept = ora_accept_draw(seed, t, color, k) < tb.thr[sv + 1][b][h + 4];
+                        if (accept) *c = (int8_t)s2;
+                    }
+                }
+        }
+    }
+    return 0;
+}

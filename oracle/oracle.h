@@ -74,6 +74,18 @@ void ora_corr(const int8_t* s, int64_t L, int mode, const int32_t* r, int nr,
 /* Schwinger-Dyson histogram: hist[k] = #sites with sigma*h = k - 4. */
 void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9]);
 
+/* Light-cone windows of a large lattice.  patch[P*P] holds the sites
+ * (x0 + i, y0 + j) mod L of an L x L lattice (row j, column i).  The
+ * window init writes their initial state; the window sweep applies the same
+ * update rule with colours and random draws of the global coordinates, to
+ * the sites whose four neighbours lie in the patch (the outer ring stays
+ * frozen).  After n sweeps the sites at least 2n from the patch edge equal
+ * those of the full lattice: a half-sweep moves information by one site. */
+int ora_init_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model, int64_t L, uint64_t seed,
+                    int init_state);
+int ora_sweep_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model, int64_t L, uint64_t seed,
+                     int64_t t0, int64_t n, double beta, double D);
+
 /* Runs n sweeps one at a time and records B, M, Q after each. */
 int  ora_series(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0, int64_t n,
                 double beta, double D, int64_t* Bs, int64_t* Ms, int64_t* Qs);

@@ -540,3 +540,23 @@ def test_schedule_worked_values():
     assert oracle.schedule_pow2(1000) == [2**k for k in range(10)]
     assert oracle.schedule_pow2(2000) == [2**k for k in range(11)]
     assert set(oracle.schedule_pow2(2000)) <= set(oracle.schedule_paper(2000))
+
+
+# --------------------------------------------------------------------------
+# Light-cone windows: the window mode equals the full-lattice oracle on the
+# sites at least 2n from the patch edge (and differs near the edge, which
+# shows the frozen ring matters).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("model,D", [(oracle.ISING, 0.0), (oracle.BC, 1.0)])
+def test_light_cone_window_matches_full_lattice(model, D):
+    L, seed, n, P = 64, 1234, 5, 40
+    full = oracle.init(model, L, seed)
+    oracle.sweep(full, model, seed, 0, n, 0.5, D)
+    inner = 2 * n
+    for (x0, y0) in [(0, 0), (50, 3), (40, 45), (13, 60)]:
+        win = oracle.window_run(model, L, seed, x0, y0, P, n, 0.5, D)
+        ys = (y0 + np.arange(P)) % L
+        xs = (x0 + np.arange(P)) % L
+        ref = full[np.ix_(ys, xs)]
+        assert np.array_equal(win[inner:P - inner, inner:P - inner], ref[inner:P - inner, inner:P - inner])
+        assert not np.array_equal(win, ref)
