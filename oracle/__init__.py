@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-ISING, BC = 0, 1
+ISING, BC, ISING_LUT = 0, 1, 2
 INIT_RANDOM, INIT_UP, INIT_DOWN, INIT_ZERO = 0, 1, 2, 3
 CORR_FULL, CORR_PROTOCOL = 1, 2
 
@@ -53,6 +53,11 @@ def lib():
         L.ora_proposal_bit.restype = ctypes.c_int
         L.ora_init_draw.argtypes = [u64, u64]
         L.ora_init_draw.restype = u32
+        L.ora_lut_table.argtypes = [ctypes.c_double, P(u64)]
+        L.ora_lut_lookup.argtypes = [P(u64), u32]
+        L.ora_lut_lookup.restype = ctypes.c_int
+        L.ora_lut_draw.argtypes = [u64, u32, ctypes.c_int, ctypes.c_int, u64]
+        L.ora_lut_draw.restype = u32
         L.ora_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
         L.ora_threshold.restype = u32
         L.ora_ising_flip_prob.argtypes = [ctypes.c_int, ctypes.c_double]
@@ -110,6 +115,21 @@ def proposal_bit(seed, t, color, k):
 
 def init_draw(seed, n):
     return int(lib().ora_init_draw(seed, n))
+
+
+def lut_table(beta):
+    T = (ctypes.c_uint64 * 16)()
+    lib().ora_lut_table(float(beta), T)
+    return [int(v) for v in T]
+
+
+def lut_lookup(T, u):
+    arr = (ctypes.c_uint64 * 16)(*T)
+    return int(lib().ora_lut_lookup(arr, u))
+
+
+def lut_draw(seed, t, color, e, g):
+    return int(lib().ora_lut_draw(seed, t, color, e, g))
 
 
 def threshold(beta, dE):

@@ -109,6 +109,53 @@ uint32_t ora_init_draw(uint64_t seed, uint64_t n)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Non-uniform random bits (section 3.2).  One 32-bit uniform yields four    */
+/* bits, each set with probability p = e^{-4 beta}, by a search in a sorted  */
+/* table of 16 entries.  The table's construction is given only in a cited  */
+/* reference; reading: entry k is the cumulative probability of the patterns */
+/* 0 .. k-1 (pattern bits independent Bernoulli(p)) scaled by 2^32 and      */
+/* floored; the search returns the largest k whose entry is <= u, so        */
+/* pattern k is drawn with probability (T[k+1] - T[k]) / 2^32.              */
+/* Draws: group g = k >> 2 of in-colour sites, stream e, counter             */
+/* (g>>2 lo, g>>2 hi, t, 8 + 2 colour + e), output word g & 3; bit j of the  */
+/* pattern belongs to site 4g + j.                                          */
+/* ------------------------------------------------------------------------ */
+void ora_lut_table(double beta, uint64_t T[16])
+{
+    double p = exp(-4.0 * beta);
+    double cum = 0.0;
+    int k, j;
+    for (k = 0; k < 16; k++) {
+        double prob = 1.0;
+        T[k] = (uint64_t)floor(ldexp(cum, 32));
+        for (j = 0; j < 4; j++)
+            prob *= ((k >> j) & 1) ? p : (1.0 - p);
+        cum += prob;
+    }
+}
+
+int ora_lut_lookup(const uint64_t T[16], uint32_t u)
+{
+    int k, best = 0;
+    for (k = 0; k < 16; k++)
+        if (T[k] <= (uint64_t)u) best = k;
+    return best;
+}
+
+uint32_t ora_lut_draw(uint64_t seed, uint32_t t, int color, int e, uint64_t g)
+{
+    uint32_t key[2], ctr[4], out[4];
+    uint64_t block = g >> 2;
+    seed_key(seed, key);
+    ctr[0] = (uint32_t)(block & 0xFFFFFFFFu);
+    ctr[1] = (uint32_t)(block >> 32);
+    ctr[2] = t;
+    ctr[3] = (uint32_t)(8 + 2 * color + e);
+    ora_philox4x32_10(ctr, key, out);
+    return out[g & 3];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Acceptance thresholds.  Metropolis accepts a move that raises the energy  */
 /* by dE with probability exp(-beta dE) (section 3.2 states it for the Ising */
 /* case: e^{-4 beta} with three aligned neighbours, e^{-8 beta} with four;   */
@@ -166,8 +213,8 @@ int ora_init(int8_t* s, int model, int64_t L, uint64_t seed, int init_state)
 {
     int64_t n, N = L * L;
     if (L < 3) return -1;
-    if (model != ORA_ISING && model != ORA_BC) return -1;
-    if (init_state == ORA_INIT_ZERO && model == ORA_ISING) return -1;
+    if (model != ORA_ISING && model != ORA_BC && model != ORA_ISING_LUT) return -1;
+    if (init_state == ORA_INIT_ZERO && model != ORA_BC) return -1;
     for (n = 0; n < N; n++) {
         int v;
         if (init_state == ORA_INIT_UP) v = 1;
@@ -175,7 +222,7 @@ int ora_init(int8_t* s, int model, int64_t L, uint64_t seed, int init_state)
         else if (init_state == ORA_INIT_ZERO) v = 0;
         else {
             uint32_t w = ora_init_draw(seed, (uint64_t)n);
-            if (model == ORA_ISING)
+            if (model != ORA_BC)
                 v = (w < 0x80000000u) ? 1 : -1;
             else
                 v = (int)(((uint64_t)w * 3u) >> 32) - 1;
@@ -202,6 +249,7 @@ static int8_t at(const int8_t* s, int64_t L, int64_t x, int64_t y)
 
 struct sweep_tables {
     uint32_t T4, T8;                  /* Ising: e^{-4 beta}, e^{-8 beta} */
+    uint64_t lut[16];                 /* Ising with table-driven random bits */
     uint32_t thr[3][2][9];            /* Blume-Capel: [s+1][b][h+4] */
     int      always[3][2][9];
 };
@@ -210,6 +258,10 @@ static void build_tables(struct sweep_tables* tb, int model, double beta, double
 {
     int si, b, hi;
     memset(tb, 0, sizeof(*tb));
+    if (model == ORA_ISING_LUT) {
+        ora_lut_table(beta, tb->lut);
+        return;
+    }
     if (model == ORA_ISING) {
         tb->T4 = ora_threshold(beta, 4.0);
         tb->T8 = ora_threshold(beta, 8.0);
@@ -248,6 +300,30 @@ static int64_t update_site(int8_t* s, int model, int64_t L, uint64_t seed, uint3
     h = nb[0] + nb[1] + nb[2] + nb[3];
     *dq = 0;
 
+    if (model == ORA_ISING_LUT) {
+        /* section 3.2: exp4 = random bits, exp8 = random bits & exp4;
+         * flip = (eq4 & exp8) | (eq3 & exp4) | (~eq4 & ~eq3) */
+        int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
+        int flip;
+        if (aligned <= 2) {
+            flip = 1;
+        } else {
+            uint64_t g = k >> 2;
+            int j = (int)(k & 3);
+            int exp4 = (ora_lut_lookup(tb->lut, ora_lut_draw(seed, t, color, 0, g)) >> j) & 1;
+            if (aligned == 3) {
+                flip = exp4;
+            } else {
+                int exp8 = (ora_lut_lookup(tb->lut, ora_lut_draw(seed, t, color, 1, g)) >> j) & 1;
+                flip = exp8 & exp4;
+            }
+        }
+        if (flip) {
+            s[n] = (int8_t)(-sv);
+            return (int64_t)(-2 * sv * h);
+        }
+        return 0;
+    }
     if (model == ORA_ISING) {
         int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
         int flip;
@@ -289,7 +365,7 @@ int ora_sweep(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0,
     int64_t it;
     int64_t accB = 0, accQ = 0;
     if (L < 3) return -1;
-    if (model != ORA_ISING && model != ORA_BC) return -1;
+    if (model != ORA_ISING && model != ORA_BC && model != ORA_ISING_LUT) return -1;
     if (beta != beta || beta < 0.0) return -2;
     if (D != D) return -3;
     if (t0 < 0 || n < 0 || t0 + n > 4294967296LL) return -4;
@@ -470,7 +546,7 @@ static int init_value(int model, uint64_t seed, int init_state, uint64_t n)
     if (init_state == ORA_INIT_ZERO) return 0;
     {
         uint32_t w = ora_init_draw(seed, n);
-        if (model == ORA_ISING) return (w < 0x80000000u) ? 1 : -1;
+        if (model != ORA_BC) return (w < 0x80000000u) ? 1 : -1;
         return (int)(((uint64_t)w * 3u) >> 32) - 1;
     }
 }
@@ -480,8 +556,8 @@ int ora_init_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model,
 {
     int64_t i, j;
     if (L < 3 || P < 3 || P > L) return -1;
-    if (model != ORA_ISING && model != ORA_BC) return -1;
-    if (init_state == ORA_INIT_ZERO && model == ORA_ISING) return -1;
+    if (model != ORA_ISING && model != ORA_BC && model != ORA_ISING_LUT) return -1;
+    if (init_state == ORA_INIT_ZERO && model != ORA_BC) return -1;
     for (j = 0; j < P; j++)
         for (i = 0; i < P; i++) {
             int64_t x = ((x0 + i) % L + L) % L, y = ((y0 + j) % L + L) % L;
@@ -496,7 +572,7 @@ int ora_sweep_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model
     struct sweep_tables tb;
     int64_t it;
     if (L < 3 || P < 3 || P > L || (L % 2) != 0) return -1;
-    if (model != ORA_ISING && model != ORA_BC) return -1;
+    if (model != ORA_ISING && model != ORA_BC && model != ORA_ISING_LUT) return -1;
     if (beta != beta || beta < 0.0) return -2;
     if (D != D) return -3;
     if (t0 < 0 || n < 0 || t0 + n > 4294967296LL) return -4;
@@ -523,6 +599,17 @@ int ora_sweep_window(int8_t* patch, int64_t P, int64_t x0, int64_t y0, int model
                         int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
                         int flip = aligned <= 2;
                         if (!flip) flip = ora_accept_draw(seed, t, color, k) < (aligned == 3 ? tb.T4 : tb.T8);
+                        if (flip) *c = (int8_t)(-sv);
+                    } else if (model == ORA_ISING_LUT) {
+                        int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
+                        int flip = aligned <= 2;
+                        if (!flip) {
+                            int j = (int)(k & 3);
+                            int e4 = (ora_lut_lookup(tb.lut, ora_lut_draw(seed, t, color, 0, k >> 2)) >> j) & 1;
+                            flip = e4;
+                            if (aligned == 4 && e4)
+                                flip = (ora_lut_lookup(tb.lut, ora_lut_draw(seed, t, color, 1, k >> 2)) >> j) & 1;
+                        }
                         if (flip) *c = (int8_t)(-sv);
                     } else {
                         int b = ora_proposal_bit(seed, t, color, k);

@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-enum { ORA_ISING = 0, ORA_BC = 1 };
+enum { ORA_ISING = 0, ORA_BC = 1, ORA_ISING_LUT = 2 };
 enum { ORA_INIT_RANDOM = 0, ORA_INIT_UP = 1, ORA_INIT_DOWN = 2, ORA_INIT_ZERO = 3 };
 enum { ORA_CORR_FULL = 1, ORA_CORR_PROTOCOL = 2 };
 
@@ -38,6 +38,17 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 uint32_t ora_accept_draw(uint64_t seed, uint32_t t, int color, uint64_t k);
 int      ora_proposal_bit(uint64_t seed, uint32_t t, int color, uint64_t k);
 uint32_t ora_init_draw(uint64_t seed, uint64_t n);
+
+/* Non-uniform random bits of section 3.2 (model ORA_ISING_LUT): 16 sorted
+ * thresholds T[k] = floor(2^32 C_k), C_k the probability of the 4-bit
+ * patterns 0..k-1 when each bit is set independently with p = exp(-4 beta);
+ * a 32-bit uniform u selects the pattern max{k : T[k] <= u}.  T[k] may be
+ * 2^32 (never selected), hence 64-bit. */
+void     ora_lut_table(double beta, uint64_t T[16]);
+int      ora_lut_lookup(const uint64_t T[16], uint32_t u);
+/* The draw feeding the 4 random bits of in-colour sites 4g .. 4g+3, for
+ * stream e (0: exp4, 1: the word ANDed into exp8). */
+uint32_t ora_lut_draw(uint64_t seed, uint32_t t, int color, int e, uint64_t g);
 
 /* Acceptance threshold floor(2^32 exp(-beta dE)) clamped to 2^32-1, dE > 0. */
 uint32_t ora_threshold(double beta, double dE);

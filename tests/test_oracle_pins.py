@@ -560,3 +560,115 @@ def test_light_cone_window_matches_full_lattice(model, D):
         ref = full[np.ix_(ys, xs)]
         assert np.array_equal(win[inner:P - inner, inner:P - inner], ref[inner:P - inner, inner:P - inner])
         assert not np.array_equal(win, ref)
+
+
+# --------------------------------------------------------------------------
+# Table-driven random bits (section 3.2) for the 1-bit Ising mode.
+# --------------------------------------------------------------------------
+def _exact_table(beta):
+    from fractions import Fraction
+    p = Fraction(math.exp(-4.0 * beta))          # the same double p, then exact arithmetic
+    T, cum = [], Fraction(0)
+    for k in range(16):
+        T.append(math.floor(cum * 2**32))
+        prob = Fraction(1)
+        for j in range(4):
+            prob *= p if (k >> j) & 1 else (1 - p)
+        cum += prob
+    return T, float(p)
+
+
+@pytest.mark.parametrize("beta", [0.1, BETA_C, BETA_C / 0.9, 1.0, 3.0])
+def test_lut_table_against_exact_rationals(beta):
+    T = oracle.lut_table(beta)
+    exact, p = _exact_table(beta)
+    assert T[0] == 0 and all(a <= b for a, b in zip(T, T[1:]))
+    assert all(abs(a - b) <= 1 for a, b in zip(T, exact))
+    # each pattern bit is Bernoulli(p) and pairs are independent, to the 2^-32 grid
+    w = [((T[k + 1] if k < 15 else 2**32) - T[k]) / 2**32 for k in range(16)]
+    for j in range(4):
+        assert abs(sum(w[k] for k in range(16) if (k >> j) & 1) - p) < 20 * 2**-32
+        for i in range(j):
+            both = sum(w[k] for k in range(16) if (k >> j) & 1 and (k >> i) & 1)
+            assert abs(both - p * p) < 20 * 2**-32
+
+
+def test_lut_limits_and_lookup():
+    import bisect
+    T = oracle.lut_table(float("inf"))           # p = 0: only pattern 0
+    assert T[0] == 0 and all(v == 2**32 for v in T[1:])
+    assert oracle.lut_lookup(T, 2**32 - 1) == 0
+    T = oracle.lut_table(0.0)                    # p = 1: only pattern 15
+    assert all(v == 0 for v in T)
+    assert oracle.lut_lookup(T, 0) == 15
+    T = oracle.lut_table(BETA_C)
+    rng = np.random.default_rng(1)
+    for u in list(rng.integers(0, 2**32, 2000)) + T[1:] + [t - 1 for t in T[1:]] + [0, 2**32 - 1]:
+        assert oracle.lut_lookup(T, int(u)) == bisect.bisect_right(T, int(u)) - 1
+
+
+def test_lut_draws_use_contract_counters(rocrand_philox):
+    seed = 987654321123
+    rows, want = [], []
+    for g in [0, 1, 5, 77, 2**33 + 3]:
+        for t, c, e in [(0, 0, 0), (3, 1, 1), (9, 0, 1)]:
+            b = g >> 2
+            rows.append([b & 0xFFFFFFFF, b >> 32, t, 8 + 2 * c + e, seed & 0xFFFFFFFF, seed >> 32])
+            want.append((g, t, c, e))
+    for (g, t, c, e), out in zip(want, rocrand_philox(rows)):
+        assert oracle.lut_draw(seed, t, c, e, g) == out[g & 3]
+
+
+@pytest.mark.parametrize("beta", [0.2, BETA_C, 0.7])
+def test_lut_rule_single_site_balance(beta):
+    """Flip probabilities implied by the table: e^{-4 beta} with three aligned
+    neighbours (one stream), e^{-8 beta} with four (both streams)."""
+    T = oracle.lut_table(beta)
+    w = [((T[k + 1] if k < 15 else 2**32) - T[k]) / 2**32 for k in range(16)]
+    for j in range(4):
+        p1 = sum(w[k] for k in range(16) if (k >> j) & 1)
+        for h in (2, 4):                      # s h = 2: three aligned; 4: four aligned
+            prob = p1 if h == 2 else p1 * p1
+            assert abs(math.exp(beta * h) * prob - math.exp(-beta * h)) < 1e-7 * math.exp(beta * h)
+
+
+@pytest.mark.parametrize("beta", [0.3, BETA_C, 0.6])
+def test_lut_ising_4x4_enumeration(beta):
+    L = 4
+    exact = _enumerate_ising(L, beta)
+    s = oracle.init(oracle.ISING_LUT, L, 55)
+    oracle.sweep(s, oracle.ISING_LUT, 55, 0, 200, beta)
+    Bs, Ms, _ = oracle.series(s, oracle.ISING_LUT, 55, 200, 200000, beta)
+    for key, series in (("E", -Bs), ("M2", Ms.astype(float) ** 2), ("absM", np.abs(Ms))):
+        m, err = _binned(series)
+        assert abs(m - exact[key]) < 3 * err + 1e-12, (key, m, exact[key], err)
+
+
+def test_lut_ising_invariants():
+    s = oracle.init(oracle.ISING_LUT, 32, 4)
+    m = oracle.measure(s)
+    b_prev = m["B"]
+    for t in range(20):                       # beta = infinity: B never decreases
+        oracle.sweep(s, oracle.ISING_LUT, 4, t, 1, float("inf"))
+        b = oracle.measure(s)["B"]
+        assert b >= b_prev
+        b_prev = b
+    a = oracle.init(oracle.ISING_LUT, 32, 6)
+    r = (-a).astype(np.int8)
+    for t in range(15):                       # global flip symmetry
+        oracle.sweep(a, oracle.ISING_LUT, 6, t, 1, BETA_C)
+        oracle.sweep(r, oracle.ISING_LUT, 6, t, 1, BETA_C)
+        assert np.array_equal(r, -a)
+    c = oracle.init(oracle.ISING_LUT, 16, 3)
+    m0 = oracle.measure(c)
+    dB, _ = oracle.sweep(c, oracle.ISING_LUT, 3, 0, 10, 0.45, track=True)
+    assert oracle.measure(c)["B"] == m0["B"] + dB
+
+
+def test_lut_window_matches_full_lattice():
+    L, seed, n, P = 64, 99, 4, 36
+    full = oracle.init(oracle.ISING_LUT, L, seed)
+    oracle.sweep(full, oracle.ISING_LUT, seed, 0, n, BETA_C)
+    win = oracle.window_run(oracle.ISING_LUT, L, seed, 30, 50, P, n, BETA_C)
+    ref = full[np.ix_((50 + np.arange(P)) % L, (30 + np.arange(P)) % L)]
+    assert np.array_equal(win[2 * n:P - 2 * n, 2 * n:P - 2 * n], ref[2 * n:P - 2 * n, 2 * n:P - 2 * n])
