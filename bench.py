@@ -112,20 +112,20 @@ def replica_set(n=512, seed=3):
     return out
 
 
-def run_blume_capel(args):
-    """Blume-Capel quench, L = 2^16, T = 1.4, D = 1, random start; B/M/Q and
-    protocol C(r,t) at t = 2^k."""
+def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label):
+    """One lattice quenched from its random start and relaxed for n sweeps,
+    with B/M/Q and protocol C(r,t) at t = 2^k; whole-job and sweep-only
+    rates, the average half-sweep and its HBM and Philox fractions."""
     import torch
 
     import paper_2502_18624_amd as mcl
-    L, n = 2 ** 16, args.bc_sweeps
     stream = torch.cuda.current_stream()
-    lat = mcl.Lattice(mcl.BC, L, 1003, stream=stream)
-    lat.sweep(2, 1 / 1.4, 1.0)                       # warm-up, then restart the quench
+    lat = mcl.Lattice(model, L, seed, stream=stream)
+    lat.sweep(2, beta, D)                            # warm-up, then restart the quench
     torch.cuda.synchronize()
     mem = lat.mem
     lat.free()
-    lat = mcl.Lattice(mcl.BC, L, 1003, stream=stream, mem=mem)
+    lat = mcl.Lattice(model, L, seed, stream=stream, mem=mem)
     torch.cuda.synchronize()
     marks = [2 ** k for k in range(20) if 2 ** k <= n]
     ev, done, t_meas = [], 0, 0.0
@@ -135,7 +135,7 @@ def run_blume_capel(args):
         if m > done:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            lat.sweep(m - done, 1 / 1.4, 1.0)
+            lat.sweep(m - done, beta, D)
             b.record(stream)
             ev.append((a, b, m - done))
             done = m
@@ -149,16 +149,44 @@ def run_blume_capel(args):
     wall = time.perf_counter() - wall0
     sweep_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
     upd = float(L) * L * n
-    res = {"workload": "Blume-Capel quench, L=2^16, T=1.4, D=1.0, random start, %d sweeps, protocol C(r,t) and "
-                       "B/M/Q at t=2^k" % n,
+    half_s = sweep_ms / (2 * n) * 1e-3
+    gblocks = L * L / 2.0 * blocks_per_update / half_s / 1e9
+    res = {"workload": label,
            "updates_per_ns": round(upd / (wall * 1e9), 2),
            "sweep_only_updates_per_ns": round(upd / (sweep_ms * 1e6), 2),
            "avg_half_sweep_ms": round(sweep_ms / (2 * n), 4),
-           "hbm_frac": round(3.0 * L * L / 4.0 / (sweep_ms / (2 * n) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "hbm_frac": round(half_bytes / half_s / 1e9 / HBM_PEAK_GBS, 4),
+           "philox_frac": round(gblocks / PHILOX_PEAK_GBLOCKS, 4),
            "measure_share": round(t_meas / wall, 4),
-           "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"]},
-           "paper_context_updates_per_ns": 941}
+           "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"]}}
     lat.free()
+    return res
+
+
+def run_blume_capel(args):
+    """Blume-Capel quench, L = 2^16, T = 1.4, D = 1, random start."""
+    import paper_2502_18624_amd as mcl
+    L, n = 2 ** 16, args.bc_sweeps
+    # a half-sweep reads both 4-bit planes and writes one: 3 L^2 / 4 bytes;
+    # one u32 acceptance draw plus one proposal bit per update
+    res = quench_leg(mcl.BC, L, 1003, 1 / 1.4, 1.0, n, 3.0 * L * L / 4.0, 0.25 + 1.0 / 128,
+                     "Blume-Capel quench, L=2^16, T=1.4, D=1.0, random start, %d sweeps, protocol C(r,t) and "
+                     "B/M/Q at t=2^k" % n)
+    res["paper_context_updates_per_ns"] = 941
+    return res
+
+
+def run_ising_1bit(args):
+    """Ising with one bit per spin and table-driven random bits, L = 2^17,
+    T = T_c, random start: the paper's own Ising kernel design."""
+    import paper_2502_18624_amd as mcl
+    L, n = 2 ** 17, args.lut_sweeps
+    # 1-bit planes: 3 L^2 / 16 bytes per half-sweep; two u32 draws per group
+    # of 4 sites (exp4 and exp8 bits) = 1/8 Philox block per update
+    res = quench_leg(mcl.ISING_LUT, L, 1002, BETA_C, 0.0, n, 3.0 * L * L / 16.0, 1.0 / 8,
+                     "Ising 1-bit (table-driven random bits), L=2^17, T=T_c, random start, %d sweeps, protocol "
+                     "C(r,t) and B/M at t=2^k" % n)
+    res["paper_context_updates_per_ns"] = 1797
     return res
 
 
@@ -327,6 +355,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
     ap.add_argument("--bc-sweeps", type=int, default=2000)
+    ap.add_argument("--lut-sweeps", type=int, default=2000)
     ap.add_argument("--replicas", type=int, default=512)
     ap.add_argument("--batched-sweeps", type=int, default=100)
     ap.add_argument("--serve-jobs", type=int, default=60)
@@ -339,6 +368,8 @@ def main():
     if not args.no_extras:
         log("bench: Blume-Capel L=2^16")
         res["blume_capel"] = run_blume_capel(args)
+        log("bench: Ising 1-bit L=2^17")
+        res["ising_1bit"] = run_ising_1bit(args)
         log("bench: batched vs plain")
         res["batched"] = run_batched(args)
         res["batched_over_plain"] = res["batched"]["batched_over_plain"]

@@ -52,8 +52,11 @@ extern "C" {
 
 typedef struct mcl_lattice mcl_lattice;
 
-/* Models: eq. (IM), spins +-1; eq. (BC), spins -1/0/+1 with crystal field D. */
-enum { MCL_ISING = 0, MCL_BC = 1 };
+/* Models: eq. (IM), spins +-1; eq. (BC), spins -1/0/+1 with crystal field D;
+ * MCL_ISING_LUT: eq. (IM) with 1-bit cells and the table-driven random bits
+ * of section 3.2 (see mcl_lut_table).  MCL_ISING and MCL_BC store 4-bit
+ * cells; MCL_ISING_LUT stores 1-bit cells and needs L a multiple of 256. */
+enum { MCL_ISING = 0, MCL_BC = 1, MCL_ISING_LUT = 2 };
 
 /* Initial states.  RANDOM is the T = infinity sample that a quench starts
  * from (section 1): Ising s = +1 iff w < 2^31, Blume-Capel
@@ -102,7 +105,8 @@ typedef struct mcl_measure_out {
 } mcl_measure_out;
 
 /* Device bytes lattice_init() needs for an L x L lattice of `model`: two
- * colour planes of 4-bit cells (L^2 / 2 bytes) plus measurement scratch. */
+ * colour planes of 4-bit cells (L^2 / 2 bytes; L^2 / 8 for 1-bit cells)
+ * plus measurement scratch. */
 int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes);
 
 /* a1 -- Create a handle and write the initial state (section 1: quench
@@ -137,6 +141,17 @@ int mcl_rset(int corr_mode, int64_t L, int64_t t, int32_t* r, int32_t cap, int32
  * Blume-Capel: 54 entries indexed ((s+1)*2 + b)*9 + (h+4); always[i] = 1
  * where dE <= 0.  dE = -h (s' - s) + D (s'^2 - s^2) in double, that order. */
 int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* always, int32_t cap);
+
+/* Table of MCL_ISING_LUT (section 3.2): with p = exp(-4 beta) and each of
+ * 4 pattern bits set independently with probability p, T[k] =
+ * floor(2^32 * C_k), C_k the probability of the patterns 0 .. k-1 summed in
+ * that order in double (T[0] = 0; T[k] may be 2^32).  A 32-bit draw u picks
+ * the pattern max{k : T[k] <= u}; bit j belongs to in-colour site 4g + j of
+ * group g.  Two streams per group g (e = 0: exp4, e = 1: ANDed with exp4
+ * into exp8): ctr = (g>>2 lo, g>>2 hi, t, 8 + 2c + e), output word g & 3.
+ * A site flips always with at most 2 aligned neighbours, iff its exp4 bit
+ * with 3, iff its exp8 bit with 4. */
+int mcl_lut_table(double beta, uint64_t* T16);
 
 /* Copy the lattice to host memory as L*L int8 spins, row-major [y][x].
  * Synchronous.  Used for parity checks and checkpoints. */

@@ -7,5 +7,5 @@ The work runs in hand-written HIP kernels behind the C ABI of
 supplies device memory and streams through PyTorch.
 """
 from ._lib import (BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_DOWN, INIT_RANDOM,  # noqa: F401
-                   INIT_UP, INIT_ZERO, ISING, MclError, lib)
-from .lattice import Lattice, group_sweep, query_bytes, rset, thresholds  # noqa: F401
+                   INIT_UP, INIT_ZERO, ISING, ISING_LUT, MclError, lib)
+from .lattice import Lattice, group_sweep, lut_table, query_bytes, rset, thresholds  # noqa: F401

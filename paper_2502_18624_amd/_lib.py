@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcl.so")
 
-ISING, BC = 0, 1
+ISING, BC, ISING_LUT = 0, 1, 2
 INIT_RANDOM, INIT_UP, INIT_DOWN, INIT_ZERO = 0, 1, 2, 3
 CORR_NONE, CORR_FULL, CORR_PROTOCOL = 0, 1, 2
 
@@ -58,6 +58,7 @@ SIGNATURES = {
     "sweep": (_INT, [_P, _I64, _DBL, _DBL]),
     "measure": (_INT, [_P, _INT, ctypes.POINTER(MeasureOut)]),
     "mcl_rset": (_INT, [_INT, _I64, _I64, ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I32)]),
+    "mcl_lut_table": (_INT, [_DBL, ctypes.POINTER(_U64)]),
     "mcl_thresholds": (_INT, [_INT, _DBL, _DBL, ctypes.POINTER(_U32), ctypes.POINTER(ctypes.c_uint8), _I32]),
     "lattice_read": (_INT, [_P, _P]),
     "lattice_read_window": (_INT, [_P, _I64, _I64, _I64, _I64, _P]),

@@ -47,7 +47,15 @@ int hip_fail(hipError_t e)
 
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
-bool valid_L(int64_t L) { return L >= 64 && (L % 64) == 0 && L <= (int64_t(1) << 20); }
+bool valid_model(int model) { return model == MCL_ISING || model == MCL_BC || model == MCL_ISING_LUT; }
+
+bool valid_L(int model, int64_t L)
+{
+    const int64_t q = model == MCL_ISING_LUT ? 256 : 64;
+    return L >= q && (L % q) == 0 && L <= (int64_t(1) << 20);
+}
+
+int cell_bits(int model) { return model == MCL_ISING_LUT ? 1 : 4; }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -55,13 +63,13 @@ struct Layout {
     int64_t planes, acc, rlist, cx, cy, res, zs, total, rcap;
 };
 
-Layout layout_of(int64_t L)
+Layout layout_of(int model, int64_t L)
 {
     Layout lay;
     lay.rcap = L / 2 + 1;
     int64_t off = 0;
     lay.planes = off;
-    off += align256(L * L / 2);
+    off += align256(L * L * cell_bits(model) / 8);
     lay.acc = off;
     off += align256(mcl::kAccSlots * 8);
     lay.rlist = off;
@@ -85,6 +93,33 @@ uint32_t threshold_of(double beta, double dE)
     const double scaled = std::ldexp(std::exp(-beta * dE), 32);
     if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
     return (uint32_t)std::floor(scaled);
+}
+
+// Table of the 1-bit mode (section 3.2): cumulative probabilities of the
+// 4-bit patterns in index order, each bit set with p = e^{-4 beta}.
+void lut_table64(double beta, uint64_t T[16])
+{
+    const double p = std::exp(-4.0 * beta);
+    double cum = 0.0;
+    for (int k = 0; k < 16; ++k) {
+        T[k] = (uint64_t)std::floor(std::ldexp(cum, 32));
+        double prob = 1.0;
+        for (int j = 0; j < 4; ++j) prob *= ((k >> j) & 1) ? p : (1.0 - p);
+        cum += prob;
+    }
+}
+
+mcl::LutTable lut_device_table(double beta)
+{
+    uint64_t T[16];
+    lut_table64(beta, T);
+    mcl::LutTable d;
+    d.kmax = 0;
+    for (int k = 0; k < 16; ++k) {
+        d.T[k] = T[k] > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)T[k];
+        if (T[k] <= 0xFFFFFFFFull) d.kmax = (uint32_t)k;
+    }
+    return d;
 }
 
 void ising_thresholds(double beta, uint32_t& T4, uint32_t& T8)
@@ -149,7 +184,22 @@ int check_params(const mcl_lattice* h, double beta, double D)
     return MCL_OK;
 }
 
-int8_t cell_to_spin(uint32_t word, int64_t i) { return (int8_t)((int)((word >> (4 * (i & 7))) & 0xFu) - 1); }
+// Cell i of a row (W words) as a spin, for 4-bit cells (n - 1) or 1-bit
+// cells (bit ? +1 : -1).
+int8_t cell_to_spin(const uint32_t* row, int64_t i, int cb)
+{
+    if (cb == 1) return ((row[i >> 5] >> (i & 31)) & 1u) ? (int8_t)1 : (int8_t)-1;
+    return (int8_t)((int)((row[i >> 3] >> (4 * (i & 7))) & 0xFu) - 1);
+}
+
+void spin_to_cell(uint32_t* row, int64_t i, int s, int cb)
+{
+    if (cb == 1) {
+        if (s > 0) row[i >> 5] |= 1u << (i & 31);
+        return;
+    }
+    row[i >> 3] |= (uint32_t)(s + 1) << (4 * (i & 7));
+}
 
 // ---------------------------------------------------------------------------
 // Batched path (row a9).
@@ -236,7 +286,7 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
     std::vector<int> idx[2];
     int64_t nmax = 0;
     for (int i = 0; i < count; ++i)
-        if (n[i] > 0) {
+        if (n[i] > 0 && hs[i]->model <= MCL_BC) {
             idx[hs[i]->model].push_back(i);
             nmax = std::max(nmax, n[i]);
         }
@@ -400,10 +450,18 @@ int mcl_last_hip_error(void) { return g_last_hip; }
 
 int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes)
 {
-    if (model != MCL_ISING && model != MCL_BC) return MCL_EMODEL;
-    if (!valid_L(L)) return MCL_EL;
+    if (!valid_model(model)) return MCL_EMODEL;
+    if (!valid_L(model, L)) return MCL_EL;
     if (!dev_bytes) return MCL_EARG;
-    *dev_bytes = layout_of(L).total;
+    *dev_bytes = layout_of(model, L).total;
+    return MCL_OK;
+}
+
+int mcl_lut_table(double beta, uint64_t* T16)
+{
+    if (std::isnan(beta) || beta < 0.0) return MCL_EBETA;
+    if (!T16) return MCL_EARG;
+    lut_table64(beta, T16);
     return MCL_OK;
 }
 
@@ -445,11 +503,11 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
 {
     if (!out || !dev_mem) return MCL_EARG;
     *out = nullptr;
-    if (model != MCL_ISING && model != MCL_BC) return MCL_EMODEL;
-    if (!valid_L(L)) return MCL_EL;
+    if (!valid_model(model)) return MCL_EMODEL;
+    if (!valid_L(model, L)) return MCL_EL;
     if (init_state < MCL_INIT_RANDOM || init_state > MCL_INIT_ZERO) return MCL_EINIT;
-    if (init_state == MCL_INIT_ZERO && model == MCL_ISING) return MCL_EINIT;
-    const Layout lay = layout_of(L);
+    if (init_state == MCL_INIT_ZERO && model != MCL_BC) return MCL_EINIT;
+    const Layout lay = layout_of(model, L);
     if (dev_bytes < lay.total) return MCL_ENOMEM;
     if (((uintptr_t)dev_mem & 255) != 0) return MCL_EARG;
     mcl_lattice* h = new (std::nothrow) mcl_lattice;
@@ -460,8 +518,9 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->seed = seed;
     h->t = 0;
     h->g.L = L;
-    h->g.W = L / 16;
-    h->g.Q = L / 64;
+    h->g.cb = cell_bits(model);
+    h->g.W = h->g.cb == 1 ? L / 64 : L / 16;
+    h->g.Q = h->g.cb == 1 ? L / 256 : L / 64;
     h->g.plane0 = (uint32_t*)(base + lay.planes);
     h->acc = (int64_t*)(base + lay.acc);
     h->rdev = (int32_t*)(base + lay.rlist);
@@ -471,7 +530,8 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->zs = (int8_t*)(base + lay.zs);
     h->rcap = lay.rcap;
     h->stream = (hipStream_t)hip_stream;
-    const hipError_t e = mcl::launch_init(h->g, model, init_state, seed, h->stream);
+    const hipError_t e = model == MCL_ISING_LUT ? mcl::launch_init1(h->g, init_state, seed, h->stream)
+                                                : mcl::launch_init(h->g, model, init_state, seed, h->stream);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e);
@@ -503,6 +563,14 @@ int sweep(mcl_lattice* h, int64_t n, double beta, double D)
     const int pc = check_params(h, beta, D);
     if (pc) return pc;
     if (h->t + n > (int64_t(1) << 32)) return MCL_ERANGE;
+    if (h->model == MCL_ISING_LUT) {
+        const mcl::LutTable tab = lut_device_table(beta);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < 2; ++c)
+                MCL_HIP(mcl::launch_lut_half(h->g, c, (uint32_t)(h->t + i), h->seed, tab, h->stream));
+        h->t += n;
+        return MCL_OK;
+    }
     mcl::HalfSweepArgs a{};
     a.seed = h->seed;
     mcl::BCTable tb{};
@@ -615,7 +683,7 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
 int lattice_read_packed(mcl_lattice* h, void* host, int64_t bytes)
 {
     if (!h || !host) return MCL_EARG;
-    const int64_t need = h->L * h->L / 2;
+    const int64_t need = 2 * h->L * h->g.W * 4;
     if (bytes < need) return MCL_EBUFSZ;
     MCL_HIP(hipStreamSynchronize(h->stream));
     MCL_HIP(hipMemcpyAsync(host, h->g.plane0, need, hipMemcpyDeviceToHost, h->stream));
@@ -627,7 +695,7 @@ int lattice_write_packed(mcl_lattice* h, const void* host, int64_t bytes, int64_
 {
     if (!h || !host) return MCL_EARG;
     if (t < 0 || t > (int64_t(1) << 32)) return MCL_ERANGE;
-    const int64_t need = h->L * h->L / 2;
+    const int64_t need = 2 * h->L * h->g.W * 4;
     if (bytes < need) return MCL_EBUFSZ;
     MCL_HIP(hipMemcpyAsync(h->g.plane0, host, need, hipMemcpyHostToDevice, h->stream));
     MCL_HIP(hipStreamSynchronize(h->stream));
@@ -645,8 +713,7 @@ int lattice_read(mcl_lattice* h, int8_t* host_spins)
     for (int64_t y = 0; y < L; ++y)
         for (int64_t x = 0; x < L; ++x) {
             const int c = (int)((x + y) & 1);
-            const int64_t i = x >> 1;
-            host_spins[y * L + x] = cell_to_spin(buf[(size_t)(c * L * W + y * W + (i >> 3))], i);
+            host_spins[y * L + x] = cell_to_spin(buf.data() + (size_t)(c * L * W + y * W), x >> 1, h->g.cb);
         }
     return MCL_OK;
 }
@@ -667,8 +734,7 @@ int lattice_read_window(mcl_lattice* h, int64_t x0, int64_t y0, int64_t w, int64
         for (int64_t dx = 0; dx < w; ++dx) {
             const int64_t x = (x0 + dx) % L;
             const int c = (int)((x + y) & 1);
-            const int64_t i = x >> 1;
-            host_spins[dy * w + dx] = cell_to_spin(rows[(size_t)(c * W + (i >> 3))], i);
+            host_spins[dy * w + dx] = cell_to_spin(rows.data() + (size_t)(c * W), x >> 1, h->g.cb);
         }
     }
     return MCL_OK;
@@ -683,11 +749,10 @@ int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t)
     for (int64_t y = 0; y < L; ++y)
         for (int64_t x = 0; x < L; ++x) {
             const int s = host_spins[y * L + x];
-            const bool ok = (h->model == MCL_ISING) ? (s == 1 || s == -1) : (s >= -1 && s <= 1);
+            const bool ok = (h->model != MCL_BC) ? (s == 1 || s == -1) : (s >= -1 && s <= 1);
             if (!ok) return MCL_ESPINS;
             const int c = (int)((x + y) & 1);
-            const int64_t i = x >> 1;
-            buf[(size_t)(c * L * W + y * W + (i >> 3))] |= (uint32_t)(s + 1) << (4 * (i & 7));
+            spin_to_cell(buf.data() + (size_t)(c * L * W + y * W), x >> 1, s, h->g.cb);
         }
     return lattice_write_packed(h, buf.data(), (int64_t)buf.size() * 4, t);
 }
@@ -703,9 +768,21 @@ int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const doubl
         if (pc) return pc;
         if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
     }
-    const int rc = group_run(hs, count, n, beta, D);
+    // 1-bit replicas are advanced one lattice per launch after the batched
+    // launches of the 4-bit replicas (they are independent lattices)
+    std::vector<int64_t> n4(n, n + count);
+    for (int i = 0; i < count; ++i)
+        if (hs[i]->model == MCL_ISING_LUT) n4[i] = 0;
+    const int rc = group_run(hs, count, n4.data(), beta, D);
     if (rc) return rc;
-    for (int i = 0; i < count; ++i) hs[i]->t += n[i];
+    for (int i = 0; i < count; ++i) {
+        if (hs[i]->model == MCL_ISING_LUT) {
+            const int r2 = sweep(hs[i], n[i], beta[i], D[i]);
+            if (r2) return r2;
+        } else {
+            hs[i]->t += n[i];
+        }
+    }
     return MCL_OK;
 }
 

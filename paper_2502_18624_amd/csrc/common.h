@@ -122,4 +122,11 @@ struct BCTable {
     uint32_t always[54];
 };
 
+// Table of the 1-bit Ising mode: the 16 sorted thresholds clamped to
+// 2^32 - 1 and the last index whose exact value was below 2^32.
+struct LutTable {
+    uint32_t T[16];
+    uint32_t kmax;
+};
+
 }  // namespace mcl

@@ -10,9 +10,10 @@ namespace mcl {
 
 // Geometry of one lattice in device memory (layout described in common.h).
 struct Geom {
-    int64_t L;          // linear size, multiple of 64
-    int64_t W;          // 32-bit words per plane row = L / 16
-    int64_t Q;          // 16-byte vectors per plane row = L / 64
+    int64_t L;          // linear size, multiple of 64 (256 for 1-bit cells)
+    int64_t W;          // 32-bit words per plane row: L / 16 (4-bit cells), L / 64 (1-bit)
+    int64_t Q;          // 16-byte vectors per plane row: L / 64 (4-bit cells), L / 256 (1-bit)
+    int cb;             // bits per cell: 4 or 1
     uint32_t* plane0;   // colour 0 cells; colour 1 follows at plane0 + L * W
     uint32_t* plane(int c) const { return plane0 + (c ? L * W : 0); }
     int64_t plane_words() const { return L * W; }
@@ -30,6 +31,9 @@ struct HalfSweepArgs {
     const BCTable* bc;      // Blume-Capel table (host copy, passed by value)
 };
 hipError_t launch_ising_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
+// 1-bit Ising with table-driven random bits (W = L/64, Q = L/256 in Geom).
+hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_t s);
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab, hipStream_t s);
 hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 
 // a6 / a7: measurement kernels accumulating into int64 device scratch.

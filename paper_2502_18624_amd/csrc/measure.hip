@@ -57,6 +57,57 @@ __device__ __forceinline__ void pair_counts(uint32_t a, uint32_t b, uint32_t& nz
     diff += popc(((a ^ b) >> 1) & z);
 }
 
+// Cell width traits: 4-bit cells (n = s + 1, 8 per word) and 1-bit cells
+// (bit = [s > 0], Ising only, 32 per word).
+template <int CB>
+struct Cell;
+
+template <>
+struct Cell<4> {
+    static constexpr int kPerWord = 8;
+    static constexpr int kVecShift = 6;     // 16-byte vectors per row = L >> 6
+    static constexpr int kWordShift = 4;    // words per row = L >> 4
+    static __device__ __forceinline__ void pair(uint32_t a, uint32_t b, uint32_t& nz, uint32_t& diff)
+    {
+        pair_counts(a, b, nz, diff);
+    }
+    static __device__ __forceinline__ void counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
+    {
+        cell_counts(w, np1, nm1, n0);
+    }
+    // neighbour word of cells i - 1 (even) / i + 1 (odd)
+    static __device__ __forceinline__ uint32_t left(uint32_t w, uint32_t prev) { return funnel(w, prev, 28); }
+    static __device__ __forceinline__ uint32_t right(uint32_t next, uint32_t w) { return funnel(next, w, 4); }
+    static __device__ __forceinline__ int spin(const uint32_t* __restrict__ row, uint32_t i)
+    {
+        return (int)((row[i >> 3] >> (4 * (i & 7))) & 0xFu) - 1;
+    }
+};
+
+template <>
+struct Cell<1> {
+    static constexpr int kPerWord = 32;
+    static constexpr int kVecShift = 8;
+    static constexpr int kWordShift = 6;
+    static __device__ __forceinline__ void pair(uint32_t a, uint32_t b, uint32_t& nz, uint32_t& diff)
+    {
+        nz += 32;
+        diff += popc(a ^ b);
+    }
+    static __device__ __forceinline__ void counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
+    {
+        const uint32_t c = popc(w);
+        np1 += c;
+        nm1 += 32 - c;
+    }
+    static __device__ __forceinline__ uint32_t left(uint32_t w, uint32_t prev) { return funnel(w, prev, 31); }
+    static __device__ __forceinline__ uint32_t right(uint32_t next, uint32_t w) { return funnel(next, w, 1); }
+    static __device__ __forceinline__ int spin(const uint32_t* __restrict__ row, uint32_t i)
+    {
+        return ((row[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+    }
+};
+
 // Sum v[0..N) over the workgroup (wave sums, then across the waves in LDS)
 // and add the totals to out[0..N): one atomic per value per workgroup, so
 // the device-wide atomics on a handful of addresses stay few.
@@ -105,11 +156,13 @@ __device__ __forceinline__ void block_add_xy(const int64_t (&v)[2 * N], int64_t*
 // a6: B, M, Q, counts.  One thread per 16-byte column of plane 0, walking a
 // band of rows with plane 1's rows y - 1, y, y + 1 in registers.
 // ---------------------------------------------------------------------------
+template <int CB>
 __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
                                                   uint32_t L, uint32_t rows, int64_t* __restrict__ acc)
 {
+    using C = Cell<CB>;
     __shared__ int64_t red[4][5];
-    const uint32_t Q = L >> 6, W = L >> 4;
+    const uint32_t Q = L >> C::kVecShift, W = L >> C::kWordShift;
     const uint32_t tasks = Q * (L / rows);
     uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < tasks; g += gridDim.x * blockDim.x) {
@@ -131,15 +184,15 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 const uint32_t w = pick(mid, d);
-                const uint32_t hs = odd ? funnel(d < 3 ? pick(mid, d + 1) : halo, w, 4)
-                                        : funnel(w, d > 0 ? pick(mid, d - 1) : halo, 28);
+                const uint32_t hs = odd ? C::right(d < 3 ? pick(mid, d + 1) : halo, w)
+                                        : C::left(w, d > 0 ? pick(mid, d - 1) : halo);
                 const uint32_t o = pick(own, d);
-                pair_counts(o, pick(up, d), nz, diff);
-                pair_counts(o, pick(dn, d), nz, diff);
-                pair_counts(o, w, nz, diff);
-                pair_counts(o, hs, nz, diff);
-                cell_counts(o, np1, nm1, n0);
-                cell_counts(w, np1, nm1, n0);
+                C::pair(o, pick(up, d), nz, diff);
+                C::pair(o, pick(dn, d), nz, diff);
+                C::pair(o, w, nz, diff);
+                C::pair(o, hs, nz, diff);
+                C::counts(o, np1, nm1, n0);
+                C::counts(w, np1, nm1, n0);
             }
             up = mid;
             mid = dn;
@@ -167,13 +220,15 @@ struct ShortTile {
     uint4 v[2][kTileRows][kSW + 1];
 };
 
-// Adds s * s' summed over the 8 cell pairs of two words to acc, except for
-// the Ising model, where every product is nonzero and acc counts the pairs
+// Adds s * s' summed over the cell pairs of two words to acc, except for
+// the Ising models, where every product is nonzero and acc counts the pairs
 // of opposite sign (the sum is then pairs - 2 acc).
 template <int MODEL>
 __device__ __forceinline__ void pair_acc(uint32_t a, uint32_t b, int& acc)
 {
-    if (MODEL == 0) {
+    if (MODEL == 2) {
+        acc += (int)popc(a ^ b);                  // 1-bit cells: pairs of opposite sign
+    } else if (MODEL == 0) {
         acc += (int)popc((a ^ b) & 0x22222222u);
     } else {
         const uint32_t z = ~(a | b) & 0x11111111u;
@@ -196,12 +251,13 @@ __device__ __forceinline__ void short_row(const ShortTile& T, int lr, int j, int
     for (int r = RLO; r <= RHI; ++r) {
         const int pc = C ^ (r & 1);
         const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);
+        const int mb = m * (MODEL == 2 ? 1 : 4);         // shift in bits
         const uint4 py = T.v[pc][lr + r][j];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const uint32_t o = pick(v, d);
-            const int base = d + (m >> 3);
-            const uint32_t px = (m & 7) ? funnel(w[pc][base + 1], w[pc][base], 4 * (m & 7)) : w[pc][base];
+            const int base = d + (mb >> 5);
+            const uint32_t px = (mb & 31) ? funnel(w[pc][base + 1], w[pc][base], mb & 31) : w[pc][base];
             pair_acc<MODEL>(o, px, ax[r]);
             pair_acc<MODEL>(o, pick(py, d), ay[r]);
         }
@@ -232,7 +288,7 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
 {
     __shared__ ShortTile T;
     __shared__ int64_t red[4][66];
-    const uint32_t Q = L >> 6;
+    const uint32_t Q = L >> (MODEL == 2 ? 8 : 6);
     const uint32_t nstrips = (Q + kSW - 1) / kSW;
     const uint32_t ntiles = nstrips * (L / kTH);
     const size_t plane_vecs = (size_t)L * Q;
@@ -263,15 +319,15 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             short_chunk<MODEL, 0, 10>(T, j, g, ax, ay);
             if (R > 10) short_chunk<MODEL, 11, 21>(T, j, g, ax, ay);
             if (R > 21) short_chunk<MODEL, 22, 32>(T, j, g, ax, ay);
-            pairs += 256;          // 4 rows x 2 planes x 32 cells per distance
+            pairs += MODEL == 2 ? 1024 : 256;     // 4 rows x 2 planes x cells of a vector, per distance
         }
     }
     int64_t v[66];
 #pragma unroll
     for (int k = 0; k < 33; ++k) {
         const bool on = k <= R;
-        v[k] = !on ? 0 : (MODEL == 0 ? pairs - 2 * (int64_t)ax[k] : (int64_t)ax[k]);
-        v[33 + k] = !on ? 0 : (MODEL == 0 ? pairs - 2 * (int64_t)ay[k] : (int64_t)ay[k]);
+        v[k] = !on ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)ax[k] : (int64_t)ax[k]);
+        v[33 + k] = !on ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)ay[k] : (int64_t)ay[k]);
     }
     block_add_xy<33>(v, Cx, Cy, red);
 }
@@ -283,20 +339,24 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
 // ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
 
-// Word of cells i + m .. i + m + 7 (periodic in the row of W words), where
-// cell i is cell 0 of word wd; wd + m / 8 < 2 W.
+// Word of the cells i + m .. (one word's worth, periodic in the row of W
+// words), where cell i is cell 0 of word wd; wd + m / cells-per-word < 2 W.
+template <int CB>
 __device__ __forceinline__ uint32_t shifted_word(const uint32_t* __restrict__ row, uint32_t W, uint32_t wd, uint32_t m)
 {
-    const uint32_t w0 = wrap(wd + (m >> 3), W);
+    const uint32_t mb = m * CB;
+    const uint32_t w0 = wrap(wd + (mb >> 5), W);
     const uint32_t w1 = wrap(w0 + 1, W);
-    return funnel(row[w1], row[w0], 4 * (m & 7));
+    return funnel(row[w1], row[w0], mb & 31);
 }
 
+template <int CB>
 __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restrict__ planes, uint32_t L, uint32_t rows,
                                                        const int32_t* __restrict__ rlist, int nr,
                                                        int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
 {
-    const uint32_t Q = L >> 6, W = L >> 4;
+    using Cl = Cell<CB>;
+    const uint32_t Q = L >> Cl::kVecShift, W = L >> Cl::kWordShift;
     const int j0 = blockIdx.y * kRChunk;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t q = g % Q;
@@ -327,8 +387,8 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
                         const uint32_t o = pick(v, d);
-                        pair_counts(o, pick(py, d), yn[j], yd[j]);
-                        pair_counts(o, shifted_word(prow, W, 4 * q + d, m), xn[j], xd[j]);
+                        Cl::pair(o, pick(py, d), yn[j], yd[j]);
+                        Cl::pair(o, shifted_word<CB>(prow, W, 4 * q + d, m), xn[j], xd[j]);
                     }
                 }
             }
@@ -346,17 +406,19 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// a7, sampled sources.  Zs[b * W + a] = s(16 a, 16 b) as int8.
+// a7, sampled sources.  Zs[b * (L / 16) + a] = s(16 a, 16 b) as int8.
 // ---------------------------------------------------------------------------
+// The source (16 a, 16 b) is in-plane cell 8 a of row 16 b of plane 0.
+template <int CB>
 __global__ __launch_bounds__(256) void zs_build_kernel(const uint32_t* __restrict__ plane0, uint32_t L,
                                                        int8_t* __restrict__ zs)
 {
-    const uint32_t W = L >> 4;
-    const uint32_t nb = L >> 4;
+    const uint32_t W = L >> Cell<CB>::kWordShift;
+    const uint32_t ns = L >> 4;                  // sources per row and source rows
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nb * W) return;
-    const uint32_t b = g / W, a = g - b * W;
-    zs[g] = (int8_t)((int)(plane0[(size_t)16 * b * W + a] & 0xFu) - 1);
+    if (g >= ns * ns) return;
+    const uint32_t b = g / ns, a = g - b * ns;
+    zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, 8 * a);
 }
 
 // Along x: one block per source row y = 16 b.  The row is unpacked into
@@ -365,11 +427,12 @@ constexpr int kXChunk = 16;
 
 // Cell of site (x, y) as a spin, read from the planes (used when a row of
 // int8 does not fit LDS).
+template <int CB>
 __device__ __forceinline__ int spin_at(const uint32_t* __restrict__ planes, size_t plane_words, uint32_t W, uint32_t x,
                                        uint32_t y)
 {
-    const uint32_t c = (x + y) & 1u, i = x >> 1;
-    return (int)((planes[c * plane_words + (size_t)y * W + (i >> 3)] >> (4 * (i & 7))) & 0xFu) - 1;
+    const uint32_t c = (x + y) & 1u;
+    return Cell<CB>::spin(planes + c * plane_words + (size_t)y * W, x >> 1);
 }
 
 // Persistent over source rows.  With USE_LDS the row is unpacked into L
@@ -378,7 +441,7 @@ __device__ __forceinline__ int spin_at(const uint32_t* __restrict__ planes, size
 // consecutive bytes; per-distance sums gather in LDS and leave with one
 // atomic per distance per workgroup.  The row takes most of a CU's LDS, so
 // a workgroup is 1024 threads (16 waves) to hide LDS latency.
-template <bool USE_LDS>
+template <int CB, bool USE_LDS>
 __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
                                                       const int32_t* __restrict__ rlist, int nr,
                                                       int64_t* __restrict__ Cx)
@@ -386,7 +449,8 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
     extern __shared__ int sx_lds[];                 // nr int32 sums, then the row
     int* sums = sx_lds;
     int8_t* srow = reinterpret_cast<int8_t*>(sx_lds + nr);
-    const uint32_t W = L >> 4;
+    const uint32_t W = L >> Cell<CB>::kWordShift;
+    const uint32_t NS = L >> 4;                     // sources per row
     const uint32_t P = L >> 4;                      // spins per residue class
     const size_t plane_words = (size_t)L * W;
     for (int k = threadIdx.x; k < nr; k += blockDim.x) sums[k] = 0;
@@ -400,9 +464,10 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
                 const uint32_t word = planes[c * plane_words + (size_t)y * W + wd];
                 const uint32_t par = (y + c) & 1u;              // x = 2 i + par
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t x = 2 * (8 * wd + k) + par;
-                    srow[(x & 15) * P + (x >> 4)] = (int8_t)((int)((word >> (4 * k)) & 0xFu) - 1);
+                for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
+                    const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
+                    const int sv = CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1 : (((word >> k) & 1u) ? 1 : -1);
+                    srow[(x & 15) * P + (x >> 4)] = (int8_t)sv;
                 }
             }
             __syncthreads();
@@ -411,14 +476,14 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
             int acc[kXChunk];
 #pragma unroll
             for (int k = 0; k < kXChunk; ++k) acc[k] = 0;
-            for (uint32_t a = threadIdx.x; a < W; a += blockDim.x) {
-                const int src = USE_LDS ? (int)srow[a] : spin_at(planes, plane_words, W, 16 * a, y);
+            for (uint32_t a = threadIdx.x; a < NS; a += blockDim.x) {
+                const int src = USE_LDS ? (int)srow[a] : spin_at<CB>(planes, plane_words, W, 16 * a, y);
 #pragma unroll
                 for (int k = 0; k < kXChunk; ++k) {
                     if (j0 + k < nr) {
                         const uint32_t x = wrap(16 * a + (uint32_t)rlist[j0 + k], L);
                         acc[k] += src * (USE_LDS ? (int)srow[(x & 15) * P + (x >> 4)]
-                                                 : spin_at(planes, plane_words, W, x, y));
+                                                 : spin_at<CB>(planes, plane_words, W, x, y));
                     }
                 }
             }
@@ -442,6 +507,7 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
 constexpr int kYChunk = 32;
 constexpr int kYRows = 128;
 
+template <int CB>
 __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict__ planes, uint32_t L,
                                                       const int8_t* __restrict__ zs,
                                                       const int32_t* __restrict__ rlist,
@@ -449,7 +515,8 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
                                                       const int32_t* __restrict__ res_idx, uint32_t nchunk,
                                                       uint32_t nband, uint32_t nachunk, int64_t* __restrict__ Cy)
 {
-    const uint32_t W = L >> 4;
+    const uint32_t W = L >> Cell<CB>::kWordShift;
+    const uint32_t NS = L >> 4;                             // sources per row
     uint32_t id = blockIdx.x;
     const uint32_t ac = id % nachunk;
     id /= nachunk;
@@ -461,7 +528,7 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
     const int p1 = res_off[rho + 1];
     if (p0 >= p1) return;
     const uint32_t a0 = ac * 1024u + 4u * threadIdx.x;     // first of this thread's 4 columns
-    const bool live = a0 < W;                               // W is a multiple of 4
+    const bool live = a0 < NS;                              // NS is a multiple of 4
     const size_t plane_words = (size_t)L * W;
     int acc[kYChunk];
 #pragma unroll
@@ -471,18 +538,28 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
         const uint32_t krow = band * kYRows + kk;
         if (krow >= nrows || !live) break;
         const uint32_t yt = rho + 16 * krow;
-        const uint4 tw = *reinterpret_cast<const uint4*>(planes + (yt & 1u) * plane_words + (size_t)yt * W + a0);
-        // pack cell 0 of the 4 words as int8 (n - 1)
-        const uint32_t t0 = ((tw.x & 0xFu) - 1u) & 0xFFu, t1 = ((tw.y & 0xFu) - 1u) & 0xFFu;
-        const uint32_t t2 = ((tw.z & 0xFu) - 1u) & 0xFFu, t3 = ((tw.w & 0xFu) - 1u) & 0xFFu;
-        const int tp = (int)(t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
+        // targets (16 a, yt), a = a0 .. a0 + 3: in-plane cells 8 a of row yt in
+        // plane yt & 1, packed as int8 spins
+        const uint32_t* trow = planes + (yt & 1u) * plane_words + (size_t)yt * W;
+        int tp;
+        if (CB == 4) {
+            const uint4 tw = *reinterpret_cast<const uint4*>(trow + a0);
+            const uint32_t t0 = ((tw.x & 0xFu) - 1u) & 0xFFu, t1 = ((tw.y & 0xFu) - 1u) & 0xFFu;
+            const uint32_t t2 = ((tw.z & 0xFu) - 1u) & 0xFFu, t3 = ((tw.w & 0xFu) - 1u) & 0xFFu;
+            tp = (int)(t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
+        } else {
+            // cells 8 a0 .. 8 a0 + 24 are bits 0, 8, 16, 24 of word a0 / 4;
+            // byte = bit ? 0x01 : 0xFF (no carries between bytes)
+            const uint32_t tw = trow[a0 >> 2] & 0x01010101u;
+            tp = (int)(tw | ((tw ^ 0x01010101u) * 0xFFu));
+        }
 #pragma unroll
         for (int k = 0; k < kYChunk; ++k) {
             const int p = p0 + k;
             if (p < p1) {
                 const uint32_t r = (uint32_t)rlist[res_idx[p]];
                 const uint32_t ys = wrap(yt + L - r, L);    // source row 16 b
-                const int sp = *reinterpret_cast<const int*>(zs + (size_t)(ys >> 4) * W + a0);
+                const int sp = *reinterpret_cast<const int*>(zs + (size_t)(ys >> 4) * NS + a0);
                 acc[k] = __builtin_amdgcn_sdot4(sp, tp, acc[k], false);
             }
         }
@@ -526,8 +603,12 @@ hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s)
     const int64_t rows = pick_rows(g.L, 16);
     const int64_t threads = g.Q * (g.L / rows);
     const uint32_t grid = (uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid);
-    hipLaunchKernelGGL(bmq_kernel, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
-                       (uint32_t)rows, acc);
+    if (g.cb == 1)
+        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
+                           (uint32_t)rows, acc);
+    else
+        hipLaunchKernelGGL(bmq_kernel<4>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
+                           (uint32_t)rows, acc);
     return hipGetLastError();
 }
 
@@ -541,8 +622,10 @@ hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64
     const uint32_t L = (uint32_t)g.L;
     if (model == 0)
         hipLaunchKernelGGL((corr_short_kernel<0>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
-    else
+    else if (model == 1)
         hipLaunchKernelGGL((corr_short_kernel<1>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
+    else
+        hipLaunchKernelGGL((corr_short_kernel<2>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
     return hipGetLastError();
 }
 
@@ -552,16 +635,23 @@ hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t*
     const int64_t rows = pick_rows(g.L, 16);
     const int64_t threads = 2 * g.Q * (g.L / rows);
     const uint32_t chunks = (uint32_t)((nr + kRChunk - 1) / kRChunk);
-    hipLaunchKernelGGL(corr_all_kernel, dim3((uint32_t)((threads + 255) / 256), chunks), dim3(256), 0, s, g.plane0,
-                       (uint32_t)g.L, (uint32_t)rows, r_dev, nr, Cx, Cy);
+    const dim3 grid((uint32_t)((threads + 255) / 256), chunks);
+    if (g.cb == 1)
+        hipLaunchKernelGGL(corr_all_kernel<1>, grid, dim3(256), 0, s, g.plane0, (uint32_t)g.L, (uint32_t)rows, r_dev,
+                           nr, Cx, Cy);
+    else
+        hipLaunchKernelGGL(corr_all_kernel<4>, grid, dim3(256), 0, s, g.plane0, (uint32_t)g.L, (uint32_t)rows, r_dev,
+                           nr, Cx, Cy);
     return hipGetLastError();
 }
 
-hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
+namespace {
+
+template <int CB>
+hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
-    if (a.nr <= 0) return hipSuccess;
-    const uint32_t L = (uint32_t)g.L, W = (uint32_t)g.W, nb = L / 16;
-    hipLaunchKernelGGL(zs_build_kernel, dim3((nb * W + 255) / 256), dim3(256), 0, s, g.plane0, L, a.zs);
+    const uint32_t L = (uint32_t)g.L, nb = L / 16;
+    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((nb * nb + 255) / 256), dim3(256), 0, s, g.plane0, L, a.zs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // along x: LDS holds the distance sums of a launch (<= 8192 distances
@@ -574,28 +664,36 @@ hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t 
         const bool use_lds = lds_sums + L <= 160u * 1024u;
         const size_t lds = lds_sums + (use_lds ? L : 0);
         static size_t attr_bytes[2] = {0, 0};
-        const void* fn = use_lds ? (const void*)corr_sx_kernel<true> : (const void*)corr_sx_kernel<false>;
+        const void* fn = use_lds ? (const void*)corr_sx_kernel<CB, true> : (const void*)corr_sx_kernel<CB, false>;
         if (lds > 64u * 1024u && attr_bytes[use_lds] < lds) {
             e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             attr_bytes[use_lds] = lds;
         }
         if (use_lds)
-            hipLaunchKernelGGL(corr_sx_kernel<true>, dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
+            hipLaunchKernelGGL((corr_sx_kernel<CB, true>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
                                a.Cx + j0);
         else
-            hipLaunchKernelGGL(corr_sx_kernel<false>, dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
+            hipLaunchKernelGGL((corr_sx_kernel<CB, false>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
                                a.Cx + j0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const uint32_t nchunk = (uint32_t)((a.max_per_residue + kYChunk - 1) / kYChunk);
     const uint32_t nband = (nb + kYRows - 1) / kYRows;
-    const uint32_t nachunk = (W + 1023) / 1024;
+    const uint32_t nachunk = (nb + 1023) / 1024;
     if (nchunk == 0) return hipSuccess;
-    hipLaunchKernelGGL(corr_sy_kernel, dim3(16u * nchunk * nband * nachunk), dim3(256), 0, s, g.plane0, L, a.zs, a.r,
-                       a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
+    hipLaunchKernelGGL(corr_sy_kernel<CB>, dim3(16u * nchunk * nband * nachunk), dim3(256), 0, s, g.plane0, L, a.zs,
+                       a.r, a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
+{
+    if (a.nr <= 0) return hipSuccess;
+    return g.cb == 1 ? corr_sampled<1>(g, a, s) : corr_sampled<4>(g, a, s);
 }
 
 }  // namespace mcl

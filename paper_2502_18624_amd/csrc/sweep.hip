@@ -64,6 +64,50 @@ __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ 
     dev::band_update<MODEL, HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, T4, T8, s_tab.e);
 }
 
+// a1 for the 1-bit layout: one thread per word (32 cells) of one plane.
+__global__ __launch_bounds__(256) void init1_kernel(uint32_t* __restrict__ planes, int64_t L, int64_t W,
+                                                    int init_state, uint32_t k0, uint32_t k1)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * L * W) return;
+    const int color = (int)(g / (L * W));
+    const int64_t rem = g - (int64_t)color * L * W;
+    const int64_t y = rem / W;
+    const int64_t wd = rem - y * W;
+    uint32_t word = 0;
+    for (int j = 0; j < 32; ++j) {
+        uint32_t bit;
+        if (init_state == 1) {
+            bit = 1;
+        } else if (init_state == 2) {
+            bit = 0;
+        } else {
+            const int64_t x = 2 * (wd * 32 + j) + ((y + color) & 1);
+            const uint64_t n = (uint64_t)(y * L + x);
+            const Philox4 o = philox4x32_10(dev::lo32(n >> 2), dev::hi32(n >> 2), 0u, 4u, k0, k1);
+            bit = philox_word(o, (int)(n & 3)) < 0x80000000u ? 1u : 0u;
+        }
+        word |= bit << j;
+    }
+    planes[g] = word;
+}
+
+template <bool HI0, int COLOR>
+__global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
+                                                       uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
+                                                       uint32_t k1, LutTable tab)
+{
+    __shared__ uint32_t s_lut[16];
+    if (threadIdx.x < 16) s_lut[threadIdx.x] = tab.T[threadIdx.x];
+    __syncthreads();
+    const uint32_t Q = L >> 8;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t q = g % Q;
+    const uint32_t y0 = (g / Q) * rows;
+    if (y0 >= L) return;
+    dev::band_update_lut<HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, s_lut, tab.T[8], tab.kmax);
+}
+
 int64_t band_rows(int64_t L)
 {
     // even; deep enough to amortise the two halo rows (1/16 extra reads of
@@ -115,6 +159,35 @@ static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t
     } else {
         if (hi0) launch_model<1, true>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
         else launch_model<1, false>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_t s)
+{
+    const int64_t total = 2 * g.L * g.W;
+    hipLaunchKernelGGL(init1_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, g.plane0, g.L, g.W,
+                       init_state, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return hipGetLastError();
+}
+
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab, hipStream_t s)
+{
+    const int64_t rows = g.L >= 4096 ? 32 : 16;
+    const int64_t threads = g.Q * (g.L / rows);
+    const dim3 grid((uint32_t)((threads + 255) / 256));
+    uint32_t* own = g.plane(color);
+    const uint32_t* oth = g.plane(1 - color);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
+    // group blocks (in-colour index / 16) fit 32 bits while L^2 / 32 <= 2^32
+    const bool hi0 = (g.L * g.L / 32) <= (int64_t(1) << 32);
+    if (hi0) {
+        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
+        else hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
+    } else {
+        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
+        else hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
     }
     return hipGetLastError();
 }

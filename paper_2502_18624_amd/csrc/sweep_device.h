@@ -263,5 +263,106 @@ __device__ __forceinline__ void band_update(uint32_t* __restrict__ own, const ui
     }
 }
 
+// ---------------------------------------------------------------------------
+// 1-bit Ising with table-driven random bits (section 3.2).  Cells are single
+// bits (1 for s = +1), 32 per word, 128 per 16-byte vector.  For a word of
+// 32 cells:
+//   b_n = neighbour word ^ own word marks the misaligned neighbours; with
+//   half adders over the four b_n, eq4 = no mismatch and eq3 = exactly one;
+//   exp4 = the 4-bit patterns of 8 table draws (stream 0), exp8 = those of
+//   stream 1 ANDed with exp4; flip = (eq4 & exp8) | (eq3 & exp4) |
+//   ~(eq4 | eq3).
+// Table search: T is the 16-entry table clamped to 2^32 - 1 (in LDS), kmax
+// the last entry that was below 2^32; the pattern is min(k, kmax) with k
+// the largest index whose clamped entry is <= u, which equals the largest
+// index whose exact entry is <= u.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lut_lookup(const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax, uint32_t u)
+{
+    uint32_t k = (u >= T8) ? 8u : 0u;
+    k += (u >= T[k + 4]) ? 4u : 0u;
+    k += (u >= T[k + 2]) ? 2u : 0u;
+    k += (u >= T[k + 1]) ? 1u : 0u;
+    return k < kmax ? k : kmax;
+}
+
+// Random bits of the 32 cells whose 8 groups of 4 start at group g0 (a
+// multiple of 8): Philox blocks g0/4 and g0/4 + 1 of `stream`.
+template <bool HI0>
+__device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
+                                             const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
+{
+    uint32_t w = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t b = (g0 >> 2) + h;
+        const Philox4 P = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, stream, k0, k1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w |= lut_lookup(T, T8, kmax, philox_word(P, j)) << (4 * (4 * h + j));
+    }
+    return w;
+}
+
+template <bool HI0>
+__device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
+                                         uint32_t halo, bool odd, uint64_t kv, uint32_t t, uint32_t color,
+                                         uint32_t k0, uint32_t k1, const uint32_t* __restrict__ T, uint32_t T8,
+                                         uint32_t kmax)
+{
+    uint32_t res[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t s = pick(src, d);
+        const uint32_t w = pick(mid, d);
+        const uint32_t hs = odd ? funnel(d < 3 ? pick(mid, d + 1) : halo, w, 1)
+                                : funnel(w, d > 0 ? pick(mid, d - 1) : halo, 31);
+        const uint32_t b0 = pick(up, d) ^ s, b1 = pick(dn, d) ^ s, b2 = w ^ s, b3 = hs ^ s;
+        const uint32_t t1 = b0 ^ b1, u1 = b0 & b1, t2 = b2 ^ b3, u2 = b2 & b3;
+        const uint32_t eq4 = ~(b0 | b1 | b2 | b3);
+        const uint32_t eq3 = (t1 ^ t2) & ~(u1 | u2);
+        const uint64_t g0 = (kv + 32u * d) >> 2;
+        const uint32_t e4 = lut_word<HI0>(g0, t, 8u + 2u * color, k0, k1, T, T8, kmax);
+        const uint32_t e8 = lut_word<HI0>(g0, t, 9u + 2u * color, k0, k1, T, T8, kmax) & e4;
+        const uint32_t flip = (eq4 & e8) | (eq3 & e4) | ~(eq4 | eq3);
+        res[d] = s ^ flip;
+    }
+    return make_uint4(res[0], res[1], res[2], res[3]);
+}
+
+// One thread's share of a 1-bit half-sweep: column vector q (128 cells) of
+// rows [y0, y0 + rows) (rows even, y0 even).
+template <bool HI0, int COLOR>
+__device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
+                                                uint32_t L, uint32_t rows, uint32_t q, uint32_t y0, uint32_t t,
+                                                uint32_t k0, uint32_t k1, const uint32_t* T, uint32_t T8,
+                                                uint32_t kmax)
+{
+    const uint32_t Q = L >> 8;                  // 16-byte vectors per row
+    const uint32_t W = L >> 6;                  // words per row
+    const uint4* __restrict__ oth4 = reinterpret_cast<const uint4*>(oth) + q;
+    const uint4* pcur = oth4 + (size_t)y0 * Q;
+    uint4* pown = reinterpret_cast<uint4*>(own) + (size_t)y0 * Q + q;
+    const uint32_t* hrow = oth + (size_t)y0 * W;
+    uint64_t kv = (uint64_t)y0 * (L >> 1) + 128u * q;
+    uint4 up = *(oth4 + (size_t)(y0 == 0 ? L - 1 : y0 - 1) * Q);
+    uint4 mid = *pcur;
+    const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;
+    const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;
+    for (uint32_t r = 0; r < rows; ++r) {
+        const uint32_t y = y0 + r;
+        const bool odd = ((y + COLOR) & 1u) != 0;
+        const uint4 dn = *((y + 1 == L) ? oth4 : pcur + Q);
+        const uint4 src = *pown;
+        const uint32_t halo = hrow[odd ? hwr : hwl];
+        *pown = lut_vec<HI0>(src, up, dn, mid, halo, odd, kv, t, COLOR, k0, k1, T, T8, kmax);
+        up = mid;
+        mid = dn;
+        pcur += Q;
+        pown += Q;
+        hrow += W;
+        kv += L >> 1;
+    }
+}
+
 }  // namespace dev
 }  // namespace mcl

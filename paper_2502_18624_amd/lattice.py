@@ -9,7 +9,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_DOWN, INIT_RANDOM, INIT_UP,  # noqa: F401
-                   INIT_ZERO, ISING, MeasureOut, check, lib)
+                   INIT_ZERO, ISING, ISING_LUT, MeasureOut, check, lib)
 
 _ALIGN = 256
 
@@ -41,6 +41,13 @@ def thresholds(model: int, beta: float, D: float = 0.0):
     if model == ISING:
         return int(thr[0]), int(thr[1])
     return thr, alw.astype(bool)
+
+
+def lut_table(beta: float):
+    """The 16-entry table of the 1-bit mode (64-bit entries, up to 2^32)."""
+    T = (ctypes.c_uint64 * 16)()
+    check(lib().mcl_lut_table(float(beta), T), "mcl_lut_table")
+    return [int(v) for v in T]
 
 
 class Lattice:
@@ -119,7 +126,8 @@ class Lattice:
         check(lib().lattice_write(self._h, s.ctypes.data_as(ctypes.c_void_p), int(t)), "lattice_write")
 
     def read_packed(self) -> np.ndarray:
-        buf = np.empty(self.L * self.L // 2, dtype=np.uint8)
+        bits = 1 if self.model == ISING_LUT else 4
+        buf = np.empty(self.L * self.L * bits // 8, dtype=np.uint8)
         check(lib().lattice_read_packed(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
               "lattice_read_packed")
         return buf

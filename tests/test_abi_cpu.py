@@ -71,6 +71,20 @@ def test_query_bytes(mcl):
         mcl.query_bytes(mcl.ISING, 32)
 
 
+def test_query_bytes_one_bit(mcl):
+    for L in (256, 768, 2**16, 2**17):
+        # two 1-bit planes, then the same scratch as the 4-bit layout
+        assert L * L // 8 <= mcl.query_bytes(mcl.ISING_LUT, L) <= L * L // 8 + L * L // 256 + 64 * L + 8192
+    for L in (64, 128, 320):                    # a row of a 1-bit plane is whole 16-byte vectors
+        with pytest.raises(mcl.MclError):
+            mcl.query_bytes(mcl.ISING_LUT, L)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.05, 0.3, BETA_C, BETA_C / 0.9, BETA_C / 0.5, 3.0, 6.0, float("inf")])
+def test_lut_table_equals_oracle(mcl, beta):
+    assert mcl.lut_table(beta) == oracle.lut_table(beta)
+
+
 @pytest.mark.parametrize("beta", [0.0, 0.1, BETA_C, BETA_C / 0.9, BETA_C / 0.5, 3.0, float("inf")])
 def test_ising_thresholds_equal_oracle(mcl, beta):
     assert mcl.thresholds(mcl.ISING, beta) == oracle.ising_thresholds(beta)
@@ -105,6 +119,11 @@ def test_argument_errors_before_device_work(mcl):
     assert lib.lattice_init(ctypes.byref(h), 0, 100, 1, 0, fake, nb, None) == -2          # MCL_EL
     assert lib.lattice_init(ctypes.byref(h), 0, 256, 1, 3, fake, nb, None) == -5          # ZERO with Ising
     assert lib.lattice_init(ctypes.byref(h), 0, 256, 1, 9, fake, nb, None) == -5
+    assert lib.lattice_init(ctypes.byref(h), 2, 320, 1, 0, fake, nb, None) == -2          # 1-bit: L % 256
+    assert lib.lattice_init(ctypes.byref(h), 2, 256, 1, 3, fake, nb, None) == -5          # ZERO, 1-bit Ising
+    assert lib.mcl_lut_table(float("nan"), (ctypes.c_uint64 * 16)()) == -3
+    assert lib.mcl_lut_table(-0.5, (ctypes.c_uint64 * 16)()) == -3
+    assert lib.mcl_lut_table(0.5, None) == -9
     assert lib.lattice_init(ctypes.byref(h), 0, 256, 1, 0, fake, nb - 1, None) == -6     # MCL_ENOMEM
     assert lib.lattice_init(ctypes.byref(h), 0, 256, 1, 0, None, nb, None) == -9          # MCL_EARG
     assert lib.sweep(None, 1, 0.4, 0.0) == -9
