@@ -25,6 +25,7 @@ struct mcl_lattice {
     int64_t* Cy;         // device: rcap entries
     int32_t* res;        // device: 17 offsets + rcap positions, sampled distances grouped by r mod 16
     int8_t* zs;          // device: (L/16)^2 sampled sources as int8
+    void* lutb;          // device: bucket table of the 1-bit mode (1-bit lattices only)
     int64_t rcap;
     hipStream_t stream;
 };
@@ -60,7 +61,7 @@ int cell_bits(int model) { return model == MCL_ISING_LUT ? 1 : 4; }
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-    int64_t planes, acc, rlist, cx, cy, res, zs, total, rcap;
+    int64_t planes, acc, rlist, cx, cy, res, zs, lutb, total, rcap;
 };
 
 Layout layout_of(int model, int64_t L)
@@ -82,6 +83,8 @@ Layout layout_of(int model, int64_t L)
     off += align256((lay.rcap + 17) * 4);
     lay.zs = off;
     off += align256((L / 16) * (L / 16));
+    lay.lutb = off;
+    if (model == MCL_ISING_LUT) off += mcl::kLutBucketBytes;
     lay.total = off;
     return lay;
 }
@@ -528,6 +531,7 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->Cy = (int64_t*)(base + lay.cy);
     h->res = (int32_t*)(base + lay.res);
     h->zs = (int8_t*)(base + lay.zs);
+    h->lutb = model == MCL_ISING_LUT ? (void*)(base + lay.lutb) : nullptr;
     h->rcap = lay.rcap;
     h->stream = (hipStream_t)hip_stream;
     const hipError_t e = model == MCL_ISING_LUT ? mcl::launch_init1(h->g, init_state, seed, h->stream)
@@ -564,10 +568,12 @@ int sweep(mcl_lattice* h, int64_t n, double beta, double D)
     if (pc) return pc;
     if (h->t + n > (int64_t(1) << 32)) return MCL_ERANGE;
     if (h->model == MCL_ISING_LUT) {
+        if (n == 0) return MCL_OK;
         const mcl::LutTable tab = lut_device_table(beta);
+        MCL_HIP(mcl::launch_lut_buckets(tab, h->lutb, h->stream));
         for (int64_t i = 0; i < n; ++i)
             for (int c = 0; c < 2; ++c)
-                MCL_HIP(mcl::launch_lut_half(h->g, c, (uint32_t)(h->t + i), h->seed, tab, h->stream));
+                MCL_HIP(mcl::launch_lut_half(h->g, c, (uint32_t)(h->t + i), h->seed, tab, h->lutb, h->stream));
         h->t += n;
         return MCL_OK;
     }

@@ -33,7 +33,12 @@ struct HalfSweepArgs {
 hipError_t launch_ising_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 // 1-bit Ising with table-driven random bits (W = L/64, Q = L/256 in Geom).
 hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_t s);
-hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab, hipStream_t s);
+// Bucket table of the 1-bit mode: kLutBucketBytes of device memory, built
+// once per beta, read by every half-sweep at that beta.
+constexpr int64_t kLutBucketBytes = 4096 * 8;
+hipError_t launch_lut_buckets(const LutTable& tab, void* buckets, hipStream_t s);
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab,
+                           const void* buckets, hipStream_t s);
 hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 
 // a6 / a7: measurement kernels accumulating into int64 device scratch.

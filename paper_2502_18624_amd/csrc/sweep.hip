@@ -92,20 +92,55 @@ __global__ __launch_bounds__(256) void init1_kernel(uint32_t* __restrict__ plane
     planes[g] = word;
 }
 
+// Bucket table of the 1-bit mode (one thread per bucket): for the draws u
+// of [lo, hi] = [b 2^20, b 2^20 + 2^20 - 1], klo = max{k <= kmax : T[k] <= lo}
+// and `inner` counts the thresholds in (lo, hi].  The sorted table makes
+// the answer klo below the one inner threshold T[klo + 1] and klo + 1 from
+// it on; with none inside it is klo throughout.
+__global__ __launch_bounds__(256) void lut_bucket_kernel(LutTable tab, uint2* __restrict__ out)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= (uint32_t)dev::kLutBuckets) return;
+    const uint32_t lo = b << 20, hi = lo + 0xFFFFFu;
+    uint32_t klo = 0, inner = 0;
+    for (uint32_t k = 1; k < 16; ++k) {
+        if (k > tab.kmax) break;
+        if (tab.T[k] <= lo) klo = k;
+        else if (tab.T[k] <= hi) ++inner;
+    }
+    uint2 e;
+    if (inner == 1 || (inner == 0 && klo < tab.kmax)) {
+        e = make_uint2(tab.T[klo + 1], klo);         // next threshold (never reached if outside)
+    } else if (inner == 0 && hi != 0xFFFFFFFFu) {
+        e = make_uint2(0xFFFFFFFFu, klo);             // above every draw of the bucket
+    } else if (inner == 0 && klo >= 1) {
+        e = make_uint2(0u, klo - 1);                  // below every draw of the bucket
+    } else {
+        e = make_uint2(0u, 0x80000000u);              // exact search
+    }
+    out[b] = e;
+}
+
 template <bool HI0, int COLOR>
 __global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
                                                        uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
-                                                       uint32_t k1, LutTable tab)
+                                                       uint32_t k1, LutTable tab, const uint2* __restrict__ buckets)
 {
     __shared__ uint32_t s_lut[16];
+    __shared__ uint2 s_b[dev::kLutBuckets];
     if (threadIdx.x < 16) s_lut[threadIdx.x] = tab.T[threadIdx.x];
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(buckets);
+        uint4* dst = reinterpret_cast<uint4*>(s_b);
+        for (uint32_t i = threadIdx.x; i < (uint32_t)dev::kLutBuckets / 2; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
     const uint32_t Q = L >> 8;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t q = g % Q;
     const uint32_t y0 = (g / Q) * rows;
     if (y0 >= L) return;
-    dev::band_update_lut<HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, s_lut, tab.T[8], tab.kmax);
+    dev::band_update_lut<HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, s_b, s_lut, tab.T[8], tab.kmax);
 }
 
 int64_t band_rows(int64_t L)
@@ -171,8 +206,17 @@ hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab, hipStream_t s)
+hipError_t launch_lut_buckets(const LutTable& tab, void* buckets, hipStream_t s)
 {
+    hipLaunchKernelGGL(lut_bucket_kernel, dim3(dev::kLutBuckets / 256), dim3(256), 0, s, tab,
+                       reinterpret_cast<uint2*>(buckets));
+    return hipGetLastError();
+}
+
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab,
+                           const void* buckets, hipStream_t s)
+{
+    const uint2* bk = reinterpret_cast<const uint2*>(buckets);
     const int64_t rows = g.L >= 4096 ? 32 : 16;
     const int64_t threads = g.Q * (g.L / rows);
     const dim3 grid((uint32_t)((threads + 255) / 256));
@@ -183,11 +227,11 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, 
     // group blocks (in-colour index / 16) fit 32 bits while L^2 / 32 <= 2^32
     const bool hi0 = (g.L * g.L / 32) <= (int64_t(1) << 32);
     if (hi0) {
-        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
-        else hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
+        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
+        else hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
     } else {
-        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
-        else hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab);
+        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
+        else hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
     }
     return hipGetLastError();
 }

@@ -303,11 +303,39 @@ __device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t s
     return w;
 }
 
+// Bucketed lookup.  Bucket b = u >> 20 (4096 buckets) holds (Tn, kw) with
+// max{k : T[k] <= u} = kw + [u >= Tn] for every u of the bucket; buckets
+// where no such pair exists (two or more thresholds inside) have bit 31 of
+// kw set, and a word with any such draw takes the exact search instead.
+constexpr int kLutBuckets = 4096;
+
+template <bool HI0>
+__device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
+                                                  const uint2* __restrict__ B, const uint32_t* __restrict__ T,
+                                                  uint32_t T8, uint32_t kmax)
+{
+    uint32_t w = 0, flags = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t b = (g0 >> 2) + h;
+        const Philox4 P = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, stream, k0, k1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t u = philox_word(P, j);
+            const uint2 e = B[u >> 20];
+            flags |= e.y;
+            w |= (e.y + (u >= e.x ? 1u : 0u)) << (4 * (4 * h + j));
+        }
+    }
+    if (flags >> 31) w = lut_word<HI0>(g0, t, stream, k0, k1, T, T8, kmax);
+    return w;
+}
+
 template <bool HI0>
 __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
                                          uint32_t halo, bool odd, uint64_t kv, uint32_t t, uint32_t color,
-                                         uint32_t k0, uint32_t k1, const uint32_t* __restrict__ T, uint32_t T8,
-                                         uint32_t kmax)
+                                         uint32_t k0, uint32_t k1, const uint2* __restrict__ B,
+                                         const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
 {
     uint32_t res[4];
 #pragma unroll
@@ -321,8 +349,8 @@ __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, cons
         const uint32_t eq4 = ~(b0 | b1 | b2 | b3);
         const uint32_t eq3 = (t1 ^ t2) & ~(u1 | u2);
         const uint64_t g0 = (kv + 32u * d) >> 2;
-        const uint32_t e4 = lut_word<HI0>(g0, t, 8u + 2u * color, k0, k1, T, T8, kmax);
-        const uint32_t e8 = lut_word<HI0>(g0, t, 9u + 2u * color, k0, k1, T, T8, kmax) & e4;
+        const uint32_t e4 = lut_word_fast<HI0>(g0, t, 8u + 2u * color, k0, k1, B, T, T8, kmax);
+        const uint32_t e8 = lut_word_fast<HI0>(g0, t, 9u + 2u * color, k0, k1, B, T, T8, kmax) & e4;
         const uint32_t flip = (eq4 & e8) | (eq3 & e4) | ~(eq4 | eq3);
         res[d] = s ^ flip;
     }
@@ -334,8 +362,8 @@ __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, cons
 template <bool HI0, int COLOR>
 __device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
                                                 uint32_t L, uint32_t rows, uint32_t q, uint32_t y0, uint32_t t,
-                                                uint32_t k0, uint32_t k1, const uint32_t* T, uint32_t T8,
-                                                uint32_t kmax)
+                                                uint32_t k0, uint32_t k1, const uint2* B, const uint32_t* T,
+                                                uint32_t T8, uint32_t kmax)
 {
     const uint32_t Q = L >> 8;                  // 16-byte vectors per row
     const uint32_t W = L >> 6;                  // words per row
@@ -354,7 +382,7 @@ __device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, cons
         const uint4 dn = *((y + 1 == L) ? oth4 : pcur + Q);
         const uint4 src = *pown;
         const uint32_t halo = hrow[odd ? hwr : hwl];
-        *pown = lut_vec<HI0>(src, up, dn, mid, halo, odd, kv, t, COLOR, k0, k1, T, T8, kmax);
+        *pown = lut_vec<HI0>(src, up, dn, mid, halo, odd, kv, t, COLOR, k0, k1, B, T, T8, kmax);
         up = mid;
         mid = dn;
         pcur += Q;

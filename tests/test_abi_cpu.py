@@ -73,8 +73,8 @@ def test_query_bytes(mcl):
 
 def test_query_bytes_one_bit(mcl):
     for L in (256, 768, 2**16, 2**17):
-        # two 1-bit planes, then the same scratch as the 4-bit layout
-        assert L * L // 8 <= mcl.query_bytes(mcl.ISING_LUT, L) <= L * L // 8 + L * L // 256 + 64 * L + 8192
+        # two 1-bit planes, the scratch of the 4-bit layout, and the 32 KiB bucket table
+        assert L * L // 8 + 32768 <= mcl.query_bytes(mcl.ISING_LUT, L) <= L * L // 8 + L * L // 256 + 64 * L + 8192 + 32768
     for L in (64, 128, 320):                    # a row of a 1-bit plane is whole 16-byte vectors
         with pytest.raises(mcl.MclError):
             mcl.query_bytes(mcl.ISING_LUT, L)

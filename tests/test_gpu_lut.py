@@ -45,6 +45,7 @@ def test_init_parity(mcl, init, L):
 CASES = [
     (256, 1, 1, BETA_C / 0.9), (256, 2, 17, BETA_C), (512, 3, 3, BETA_C / 0.5), (768, 4, 5, BETA_C / 1.5),
     (256, 5, 2, INF), (1024, 6, 4, BETA_C), (512, 7, 3, 0.0), (2048, 8, 2, BETA_C / 0.9), (256, 9, 9, 3.0),
+    (512, 10, 6, 0.8), (256, 12, 4, 1.2),
 ]
 
 
@@ -57,6 +58,18 @@ def test_sweep_parity(mcl, L, seed, n, beta):
     want = _oracle_run(L, seed, 0, n, beta)
     assert lat.t == n
     assert np.array_equal(got, want), "mismatch at %d cells" % int((got != want).sum())
+
+
+def test_sweep_parity_over_beta(mcl):
+    """Many temperatures, including those where several thresholds of the
+    table fall within 2^-12 of each other (low T) and the lookup takes its
+    exact search, and beta where p^4 straddles 2^-12."""
+    L = 256
+    for i, beta in enumerate([0.05, 0.2, 0.35, BETA_C, 0.5, 0.52, 0.53, 0.6, 0.7, 1.0, 1.5, 2.0, 4.0, 8.0]):
+        lat = mcl.Lattice(LUT, L, 300 + i)
+        lat.sweep(3, beta)
+        assert np.array_equal(lat.read(), _oracle_run(L, 300 + i, 0, 3, beta)), beta
+        lat.free()
 
 
 def test_ordered_start_at_zero_temperature_stays(mcl):
