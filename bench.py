@@ -158,7 +158,8 @@ def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label)
            "hbm_frac": round(half_bytes / half_s / 1e9 / HBM_PEAK_GBS, 4),
            "philox_frac": round(gblocks / PHILOX_PEAK_GBLOCKS, 4),
            "measure_share": round(t_meas / wall, 4),
-           "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"]}}
+           "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"],
+                     "schwinger_dyson": round(mcl.schwinger_dyson(out["sd"], beta), 7)}}
     lat.free()
     return res
 
@@ -297,7 +298,8 @@ def run(args):
             out = lat.measure(mcl.CORR_PROTOCOL)
             t_meas += time.perf_counter() - tm
             measures.append({"t": out["t"], "B": out["B"], "M": out["M"], "n_r": int(len(out["r"])),
-                             "Cx1": int(out["Cx"][1]), "Cy1": int(out["Cy"][1])})
+                             "Cx1": int(out["Cx"][1]), "Cy1": int(out["Cy"][1]),
+                             "schwinger_dyson": round(mcl.schwinger_dyson(out["sd"], beta), 7)})
             log("  t=%d B=%d M=%d" % (out["t"], out["B"], out["M"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0

@@ -102,6 +102,10 @@ typedef struct mcl_measure_out {
     int64_t* nsrc;      /* out: number of sources at each distance */
     int32_t r_cap;      /* in: capacity of the four arrays */
     int32_t n_r;        /* out: number of distances (also set on MCL_EBUFSZ) */
+    int64_t sd[9];      /* out: sd[k] = number of sites with sigma h = k - 4, h the sum of
+                         * the four neighbours: the histogram behind the Schwinger-Dyson
+                         * check of section 4 (eq. SDI), whose right-hand side is
+                         * sum_k sd[k] exp(-2 beta (k - 4)) / L^2 */
 } mcl_measure_out;
 
 /* Device bytes lattice_init() needs for an L x L lattice of `model`: two

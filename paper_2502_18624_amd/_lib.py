@@ -39,7 +39,7 @@ class MeasureOut(ctypes.Structure):
         ("counts", ctypes.c_int64 * 3), ("invalid", ctypes.c_int64),
         ("r", ctypes.POINTER(ctypes.c_int32)), ("Cx", ctypes.POINTER(ctypes.c_int64)),
         ("Cy", ctypes.POINTER(ctypes.c_int64)), ("nsrc", ctypes.POINTER(ctypes.c_int64)),
-        ("r_cap", ctypes.c_int32), ("n_r", ctypes.c_int32),
+        ("r_cap", ctypes.c_int32), ("n_r", ctypes.c_int32), ("sd", ctypes.c_int64 * 9),
     ]
 
 

@@ -676,6 +676,7 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
     out->counts[1] = acc[4];
     out->counts[2] = acc[2];
     out->invalid = h->L * h->L - acc[2] - acc[3] - acc[4];
+    for (int k = 0; k < 9; ++k) out->sd[k] = acc[5 + k];
     out->t = h->t;
     const int64_t all_src = h->L * h->L;
     const int64_t sampled_src = (h->L / 16) * (h->L / 16);

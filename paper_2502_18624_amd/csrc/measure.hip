@@ -156,53 +156,113 @@ __device__ __forceinline__ void block_add_xy(const int64_t (&v)[2 * N], int64_t*
 // a6: B, M, Q, counts.  One thread per 16-byte column of plane 0, walking a
 // band of rows with plane 1's rows y - 1, y, y + 1 in registers.
 // ---------------------------------------------------------------------------
+// Histogram of t = sigma h + 4 (0..8) over the cells of word o, whose four
+// neighbour words are a, b (vertical), c (same row) and d (horizontal).
+// 4-bit cells: the neighbour sum S = sum n = h + 4 fits a nibble, and
+// t = 4 for sigma = 0, S for sigma = +1, 8 - S for sigma = -1.
+__device__ __forceinline__ void sd_add4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t (&hist)[9])
+{
+    const uint32_t S = a + b + c + d;
+    const uint32_t m2 = ((o >> 1) & 0x11111111u) * 15u;             // sigma = +1
+    const uint32_t m0 = (~(o | (o >> 1)) & 0x11111111u) * 15u;      // sigma = -1
+    const uint32_t t = (S & m2) | ((0x88888888u - S) & m0) | (0x44444444u & ~(m0 | m2));
+    const uint32_t b0 = t & 0x11111111u, b1 = (t >> 1) & 0x11111111u;
+    const uint32_t b2 = (t >> 2) & 0x11111111u, b3 = (t >> 3) & 0x11111111u;
+    const uint32_t n0 = b0 ^ 0x11111111u, n1 = b1 ^ 0x11111111u, n2 = b2 ^ 0x11111111u, n3 = b3 ^ 0x11111111u;
+    const uint32_t lo[4] = {n0 & n1, b0 & n1, n0 & b1, b0 & b1};
+    const uint32_t hi0 = n2 & n3, hi1 = b2 & n3;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) hist[v] += popc(lo[v & 3] & (v < 4 ? hi0 : hi1));
+    hist[8] += popc(b3);
+}
+
+// 1-bit cells: t = 2 (aligned neighbours), from the four words of
+// differences d_j = neighbour ^ own.
+__device__ __forceinline__ void sd_add1(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t (&hist)[9])
+{
+    const uint32_t d0 = a ^ o, d1 = b ^ o, d2 = c ^ o, d3 = d ^ o;
+    const uint32_t t1 = d0 ^ d1, t2 = d2 ^ d3;
+    const uint32_t all_eq = ~(d0 | d1 | d2 | d3);                    // 4 aligned: t = 8
+    const uint32_t all_ne = d0 & d1 & d2 & d3;                       // 0 aligned: t = 0
+    const uint32_t one_ne = (t1 ^ t2) & ~((d0 & d1) | (d2 & d3));    // 3 aligned: t = 6
+    const uint32_t one_eq = (t1 ^ t2) & (d0 | d1) & (d2 | d3);       // 1 aligned: t = 2
+    const uint32_t c8 = popc(all_eq), c0 = popc(all_ne), c6 = popc(one_ne), c2 = popc(one_eq);
+    hist[8] += c8;
+    hist[0] += c0;
+    hist[6] += c6;
+    hist[2] += c2;
+    hist[4] += 32u - c8 - c0 - c6 - c2;
+}
+
+// One pass over both planes: B and M, Q and the value counts, and the
+// Schwinger-Dyson histogram (section 4) of sigma h over every site.  A task
+// is a column vector q of a band of rows; the thread keeps rows y - 1, y,
+// y + 1 of both planes.  Colour-0 sites carry the bonds (each bond has one
+// colour-0 end); both colours add to the counts and the histogram.
 template <int CB>
 __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
                                                   uint32_t L, uint32_t rows, int64_t* __restrict__ acc)
 {
     using C = Cell<CB>;
-    __shared__ int64_t red[4][5];
+    __shared__ int64_t red[4][14];
     const uint32_t Q = L >> C::kVecShift, W = L >> C::kWordShift;
     const uint32_t tasks = Q * (L / rows);
     uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0;
+    uint32_t hist[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) hist[k] = 0;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < tasks; g += gridDim.x * blockDim.x) {
         const uint32_t q = g % Q;
         const uint32_t y0 = (g / Q) * rows;
         const uint4* a4 = reinterpret_cast<const uint4*>(p0) + q;
         const uint4* b4 = reinterpret_cast<const uint4*>(p1) + q;
-        uint4 up = b4[(size_t)(y0 == 0 ? L - 1 : y0 - 1) * Q];
-        uint4 mid = b4[(size_t)y0 * Q];
+        const size_t yu = y0 == 0 ? L - 1 : y0 - 1;
+        uint4 aup = a4[yu * Q], amid = a4[(size_t)y0 * Q];
+        uint4 bup = b4[yu * Q], bmid = b4[(size_t)y0 * Q];
         const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;
         const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;
         for (uint32_t r = 0; r < rows; ++r) {
             const uint32_t y = y0 + r;
-            const uint32_t yd = (y + 1 == L) ? 0 : y + 1;
-            const uint4 own = a4[(size_t)y * Q];
-            const uint4 dn = b4[(size_t)yd * Q];
-            const bool odd = (y & 1u) != 0;
-            const uint32_t halo = p1[(size_t)y * W + (odd ? hwr : hwl)];
+            const size_t yd = (y + 1 == L) ? 0 : y + 1;
+            const uint4 adn = a4[yd * Q], bdn = b4[yd * Q];
+            const bool odd = (y & 1u) != 0;      // colour-0 sites of row y have x = 2 i + (y & 1)
+            // colour 0 looks right (i + 1) on odd rows, colour 1 on even rows
+            const uint32_t bhalo = p1[(size_t)y * W + (odd ? hwr : hwl)];
+            const uint32_t ahalo = p0[(size_t)y * W + (odd ? hwl : hwr)];
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
-                const uint32_t w = pick(mid, d);
-                const uint32_t hs = odd ? C::right(d < 3 ? pick(mid, d + 1) : halo, w)
-                                        : C::left(w, d > 0 ? pick(mid, d - 1) : halo);
-                const uint32_t o = pick(own, d);
-                C::pair(o, pick(up, d), nz, diff);
-                C::pair(o, pick(dn, d), nz, diff);
-                C::pair(o, w, nz, diff);
-                C::pair(o, hs, nz, diff);
-                C::counts(o, np1, nm1, n0);
-                C::counts(w, np1, nm1, n0);
+                const uint32_t wb = pick(bmid, d), wa = pick(amid, d);
+                const uint32_t hb = odd ? C::right(d < 3 ? pick(bmid, d + 1) : bhalo, wb)
+                                        : C::left(wb, d > 0 ? pick(bmid, d - 1) : bhalo);
+                const uint32_t ha = odd ? C::left(wa, d > 0 ? pick(amid, d - 1) : ahalo)
+                                        : C::right(d < 3 ? pick(amid, d + 1) : ahalo, wa);
+                C::pair(wa, pick(bup, d), nz, diff);
+                C::pair(wa, pick(bdn, d), nz, diff);
+                C::pair(wa, wb, nz, diff);
+                C::pair(wa, hb, nz, diff);
+                C::counts(wa, np1, nm1, n0);
+                C::counts(wb, np1, nm1, n0);
+                if (CB == 4) {
+                    sd_add4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
+                    sd_add4(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
+                } else {
+                    sd_add1(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
+                    sd_add1(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
+                }
             }
-            up = mid;
-            mid = dn;
+            aup = amid;
+            amid = adn;
+            bup = bmid;
+            bmid = bdn;
         }
     }
-    // acc: [0] B, [1] M, [2] #(+1), [3] #(-1), [4] #(0); invalid cells are
-    // what the three counts leave of L^2 (done on the host)
-    const int64_t v[5] = {(int64_t)nz - 2 * (int64_t)diff, (int64_t)np1 - (int64_t)nm1, (int64_t)np1,
-                          (int64_t)nm1, (int64_t)n0};
-    block_add<5>(v, acc, red);
+    // acc: [0] B, [1] M, [2] #(+1), [3] #(-1), [4] #(0), [5 + k] #(sigma h = k - 4);
+    // invalid cells are what the three counts leave of L^2 (done on the host)
+    int64_t v[14] = {(int64_t)nz - 2 * (int64_t)diff, (int64_t)np1 - (int64_t)nm1, (int64_t)np1, (int64_t)nm1,
+                     (int64_t)n0};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[5 + k] = (int64_t)hist[k];
+    block_add<14>(v, acc, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,6 +4,7 @@ and a library handle; every call marshals arguments into the C ABI of
 from __future__ import annotations
 
 import ctypes
+import math
 
 import numpy as np
 
@@ -48,6 +49,18 @@ def lut_table(beta: float):
     T = (ctypes.c_uint64 * 16)()
     check(lib().mcl_lut_table(float(beta), T), "mcl_lut_table")
     return [int(v) for v in T]
+
+
+def schwinger_dyson(sd, beta: float) -> float:
+    """Right-hand side of the Schwinger-Dyson identity (section 4, eq. SDI)
+    from the histogram of measure()["sd"]: the site average of
+    exp(-2 beta sigma h); 1 in equilibrium."""
+    n = sum(int(v) for v in sd)
+    if n == 0:
+        raise ValueError("empty histogram")
+    if not math.isfinite(beta) or beta < 0:
+        raise ValueError("beta must be finite and non-negative")
+    return math.fsum(int(v) * math.exp(-2.0 * beta * (k - 4)) for k, v in enumerate(sd) if v) / n
 
 
 class Lattice:
@@ -105,7 +118,7 @@ class Lattice:
         n = out.n_r
         return {"B": out.B, "M": out.M, "Q": out.Q, "t": out.t, "counts": list(out.counts),
                 "invalid": out.invalid, "r": r[:n].copy(), "Cx": cx[:n].copy(), "Cy": cy[:n].copy(),
-                "nsrc": ns[:n].copy()}
+                "nsrc": ns[:n].copy(), "sd": list(out.sd)}
 
     # -- host copies (parity checks, checkpoints) -------------------------
     def read(self) -> np.ndarray:

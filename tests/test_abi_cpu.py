@@ -156,3 +156,18 @@ def test_group_tuning_roundtrip_and_validation(mcl):
     assert back.rows_log2L[10] == 64 and back.use_graph == 1
     assert lib.mcl_group_tuning_set(ctypes.byref(saved)) == 0
     assert lib.group_sweep(None, 0, None, None, None) == 0     # empty group is a no-op
+
+
+@pytest.mark.parametrize("model,beta", [(0, 0.3), (0, BETA_C), (1, 0.7), (2, 1.1)])
+def test_schwinger_dyson_helper_equals_site_average(mcl, model, beta):
+    """Right-hand side of eq. SDI from the 9-bin histogram equals the site
+    average of exp(-2 beta sigma h) written out over the lattice."""
+    s = oracle.init(model, 64, 17)
+    oracle.sweep(s, model, 17, 0, 5, beta, 0.5)
+    h = np.roll(s, 1, 0) + np.roll(s, -1, 0) + np.roll(s, 1, 1) + np.roll(s, -1, 1)
+    direct = float(np.mean(np.exp(-2.0 * beta * s.astype(np.float64) * h)))
+    assert mcl.schwinger_dyson(oracle.sd_hist(s), beta) == pytest.approx(direct, rel=1e-13)
+    up = np.ones((64, 64), dtype=np.int8)
+    assert mcl.schwinger_dyson(oracle.sd_hist(up), beta) == pytest.approx(math.exp(-8 * beta), rel=1e-15)
+    with pytest.raises(ValueError):
+        mcl.schwinger_dyson([0] * 9, beta)

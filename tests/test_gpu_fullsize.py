@@ -59,6 +59,9 @@ def test_measure_invariants_at_full_size(mcl):
     assert m["M"] == m["counts"][2] - m["counts"][0]
     assert m["Q"] == m["counts"][2] + m["counts"][0] == N
     assert m["Cx"][0] == m["Q"] and m["Cy"][0] == m["Q"]
+    # Schwinger-Dyson histogram: every site once, sum of sigma h = 2 B, Ising h even
+    assert sum(m["sd"]) == N and sum((k - 4) * v for k, v in enumerate(m["sd"])) == 2 * m["B"]
+    assert all(v == 0 for v in m["sd"][1::2])
     assert np.array_equal(m["r"], oracle.rset(oracle.CORR_PROTOCOL, L, 4))
     expect_src = np.where(m["r"] <= 32, N, (L // 16) ** 2)
     assert np.array_equal(m["nsrc"], expect_src)
@@ -70,6 +73,7 @@ def test_measure_invariants_at_full_size(mcl):
     up = mcl.Lattice(mcl.ISING, L, 1, mcl.INIT_UP, mem=mem)
     m = up.measure(mcl.CORR_PROTOCOL)
     assert (m["B"], m["M"], m["Q"]) == (2 * N, N, N)
+    assert m["sd"] == [0] * 8 + [N]
     assert np.array_equal(m["Cx"], m["nsrc"]) and np.array_equal(m["Cy"], m["nsrc"])
     up.free()
 
@@ -89,5 +93,6 @@ def test_protocol_parity_at_4096(mcl, model):
     m = lat.measure(mcl.CORR_PROTOCOL)
     om = oracle.measure(s)
     assert (m["B"], m["M"], m["Q"], m["counts"]) == (om["B"], om["M"], om["Q"], om["counts"])
+    assert m["sd"] == list(oracle.sd_hist(s))
     Cx, Cy, ns = oracle.corr(s, oracle.CORR_PROTOCOL, m["r"])
     assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy) and np.array_equal(m["nsrc"], ns)

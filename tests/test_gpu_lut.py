@@ -72,6 +72,35 @@ def test_sweep_parity_over_beta(mcl):
         lat.free()
 
 
+@pytest.mark.parametrize("model,beta", [(LUT, INF), (LUT, 0.0), (0, INF)])
+def test_update_rule_truth_table(mcl, model, beta):
+    """Deterministic limits of the Ising rule (eq. IM; random bits of section
+    3.2 in the 1-bit mode).  At beta = infinity no random bit is set and a
+    spin flips iff at most 2 of its 4 neighbours are aligned; at beta = 0
+    (1-bit mode) every bit is set and every spin flips.  One sweep from a
+    random state in which all 32 (spin, neighbours) cases occur, against the
+    colour-by-colour rule written out in numpy."""
+    L = 256
+    s0 = np.random.default_rng(8).choice([-1, 1], size=(L, L)).astype(np.int8)
+
+    def nsum(a):
+        return np.roll(a, 1, 0) + np.roll(a, -1, 0) + np.roll(a, 1, 1) + np.roll(a, -1, 1)
+
+    yy, xx = np.indices((L, L))
+    bits = [(s0 > 0)] + [np.roll(s0, sh, ax) > 0 for sh, ax in ((1, 0), (-1, 0), (1, 1), (-1, 1))]
+    code = sum(b.astype(np.int64) << j for j, b in enumerate(bits))
+    assert len(np.unique(code[((xx + yy) & 1) == 0])) == 32
+    want = s0.astype(np.int64)
+    for c in (0, 1):
+        colour = ((xx + yy) & 1) == c
+        flip = colour & ((want * nsum(want) <= 0) if beta == INF else True)   # s h <= 0: at most 2 aligned
+        want = np.where(flip, -want, want)
+    lat = mcl.Lattice(model, L, 5)
+    lat.write(s0, 0)
+    lat.sweep(1, beta)
+    assert np.array_equal(lat.read(), want.astype(np.int8))
+
+
 def test_ordered_start_at_zero_temperature_stays(mcl):
     """beta = infinity from the all-up state: every site is aligned with all
     its neighbours, p = 0, so no move is ever accepted."""
@@ -114,6 +143,7 @@ def _check_measure(mcl, lat, mode):
     m = lat.measure(mode)
     om = oracle.measure(s)
     assert (m["B"], m["M"], m["Q"], m["counts"], m["invalid"]) == (om["B"], om["M"], om["Q"], om["counts"], 0)
+    assert m["sd"] == list(oracle.sd_hist(s))
     if mode != mcl.CORR_NONE:
         r = oracle.rset(mode, lat.L, lat.t)
         assert np.array_equal(m["r"], r)
@@ -146,6 +176,7 @@ def test_measure_ordered_states(mcl):
     for init, val in ((1, 1), (2, -1)):
         m = mcl.Lattice(LUT, L, 0, init).measure(mcl.CORR_PROTOCOL)
         assert (m["B"], m["M"], m["Q"]) == (2 * N, val * N, N)
+        assert m["sd"] == [0] * 8 + [N]
         assert np.array_equal(m["Cx"], m["nsrc"]) and np.array_equal(m["Cy"], m["nsrc"])
 
 
@@ -185,6 +216,8 @@ def test_light_cone_windows_at_full_size(mcl):
     assert m["invalid"] == 0 and m["counts"][1] == 0 and m["Q"] == N
     assert m["M"] == m["counts"][2] - m["counts"][0]
     assert m["Cx"][0] == N and m["Cy"][0] == N
+    assert sum(m["sd"]) == N and sum((k - 4) * v for k, v in enumerate(m["sd"])) == 2 * m["B"]
+    assert all(v == 0 for v in m["sd"][1::2])
     assert np.all(np.abs(m["Cx"]) <= m["nsrc"]) and np.all(np.abs(m["Cy"]) <= m["nsrc"])
     assert np.all(m["Cx"][1:8] > 0) and np.all(m["Cy"][1:8] > 0)
     lat.free()

@@ -120,6 +120,7 @@ def _check_measure(mcl, lat, mode):
     m = lat.measure(mode)
     om = oracle.measure(s)
     assert (m["B"], m["M"], m["Q"], m["counts"], m["invalid"]) == (om["B"], om["M"], om["Q"], om["counts"], 0)
+    assert m["sd"] == list(oracle.sd_hist(s))
     if mode != mcl.CORR_NONE:
         r = oracle.rset(mode, lat.L, lat.t)
         assert np.array_equal(m["r"], r)
@@ -154,6 +155,7 @@ def test_measure_structured_states(mcl):
         m = lat.measure(mcl.CORR_PROTOCOL)
         N = L * L
         assert m["M"] == val * N and m["Q"] == abs(val) * N and m["B"] == 2 * N * val * val
+        assert m["sd"] == ([0] * 8 + [N] if val else [0] * 4 + [N] + [0] * 4)
         assert np.array_equal(m["Cx"], abs(val) * m["nsrc"]) and np.array_equal(m["Cy"], abs(val) * m["nsrc"])
 
 
