@@ -30,10 +30,7 @@ __global__ __launch_bounds__(256) void group_half_kernel(const GroupDesc* __rest
     const int i = find_replica(desc, count, blockIdx.x);
     const GroupDesc d = desc[i];
     if (s >= d.n) return;
-    if (MODEL == 1) {
-        for (uint32_t k = threadIdx.x; k < 96u; k += blockDim.x) s_tab.e[k] = tables[(size_t)d.bc * 96u + k];
-        __syncthreads();
-    }
+    if (MODEL == 1) dev::load_bc_table(s_tab, tables + (size_t)d.bc * 96u);
     const uint32_t L = d.L;
     const uint32_t Q = L >> 6;
     const uint32_t g = (blockIdx.x - d.wg_begin) * blockDim.x + threadIdx.x;

@@ -82,6 +82,43 @@ __device__ __forceinline__ uint32_t shift_in_lt(uint32_t acc, uint32_t u, uint32
     return r;
 }
 
+// High word of u + A (64-bit; one v_mad_u64_u32 with multiplier 1).  With
+// A = -E for E in [0, 2^32] it is -[u < E]: a 33-bit comparison in one
+// instruction.
+__device__ __forceinline__ uint32_t add_hi(uint32_t u, uint64_t A)
+{
+    uint64_t d;
+    asm("v_mad_u64_u32 %0, vcc, %1, 1, %2" : "=v"(d) : "v"(u), "v"(A) : "vcc");
+    return (uint32_t)(d >> 32);
+}
+
+// (x << S) | y as one v_lshl_or_b32.  Written out, an or of disjoint
+// shifted copies (or x << 4 minus x) is turned by the compiler into a
+// quarter-rate v_mul_lo_u32 by a constant.
+template <int S>
+__device__ __forceinline__ uint32_t shl_or(uint32_t x, uint32_t y)
+{
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(S), "v"(y));
+    return r;
+}
+
+// (x << S) + y as one v_lshl_add_u32 (a chain of these is otherwise
+// re-associated into multiplies).
+template <int S>
+__device__ __forceinline__ uint32_t shl_add(uint32_t x, uint32_t y)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(S), "v"(y));
+    return r;
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t shl_opaque(uint32_t x)
+{
+    return shl_or<S>(x, 0u);
+}
+
 // ({hi, lo} >> sh)[31:0], sh in 0..31 (one v_alignbit_b32).
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
 {

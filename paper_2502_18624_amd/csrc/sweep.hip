@@ -108,17 +108,18 @@ __global__ __launch_bounds__(256) void lut_bucket_kernel(LutTable tab, uint2* __
         if (tab.T[k] <= lo) klo = k;
         else if (tab.T[k] <= hi) ++inner;
     }
-    uint2 e;
+    // the answer is kw + [u >= Tn] on the bucket; stored as kw 2^32 + 2^32 - Tn
+    uint64_t A;
     if (inner == 1 || (inner == 0 && klo < tab.kmax)) {
-        e = make_uint2(tab.T[klo + 1], klo);         // next threshold (never reached if outside)
+        A = ((uint64_t)klo << 32) + (uint64_t(1) << 32) - tab.T[klo + 1];   // next threshold
     } else if (inner == 0 && hi != 0xFFFFFFFFu) {
-        e = make_uint2(0xFFFFFFFFu, klo);             // above every draw of the bucket
+        A = ((uint64_t)klo << 32) + 1u;               // Tn = 2^32 - 1, above every draw of the bucket
     } else if (inner == 0 && klo >= 1) {
-        e = make_uint2(0u, klo - 1);                  // below every draw of the bucket
+        A = (uint64_t)klo << 32;                      // kw = klo - 1, Tn = 0
     } else {
-        e = make_uint2(0u, 0x80000000u);              // exact search
+        A = uint64_t(1) << 63;                        // exact search
     }
-    out[b] = e;
+    out[b] = make_uint2((uint32_t)A, (uint32_t)(A >> 32));
 }
 
 template <bool HI0, int COLOR>

@@ -103,19 +103,63 @@ __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, co
 // ---------------------------------------------------------------------------
 // a4: Blume-Capel vector update (32 cells).  Per cell: the proposal
 // s' = ((n + 1 + b) mod 3) - 1 (n = s + 1, b the proposal bit), then a table
-// lookup on (n, b, sum of neighbour cells) gives the threshold and whether
-// dE <= 0; accept = always | (u < thr), as a 33-bit borrow
-// (0:u) - (always:thr).  Word-level: n + 1 + b and its reduction mod 3 are
-// nibble-parallel; the accept bits gate the new values in with a bit select.
+// lookup on (n, b, sum of neighbour cells) gives E = thr, or 2^32 where
+// dE <= 0, and accept = [u < E].  Word-level: n + 1 + b and its reduction
+// mod 3 are nibble-parallel, the table index of each cell is a byte built
+// for 4 cells at a time, and the accept bits gate the new values in with a
+// bit select.
 // ---------------------------------------------------------------------------
 // Spread the low 8 bits of x to bit 0 of the 8 nibbles.
 __device__ __forceinline__ uint32_t spread8(uint32_t x)
 {
     x &= 0xFFu;
-    x = (x | (x << 12)) & 0x000F000Fu;
-    x = (x | (x << 6)) & 0x03030303u;
-    x = (x | (x << 3)) & 0x11111111u;
+    x = shl_or<12>(x, x) & 0x000F000Fu;
+    x = shl_or<6>(x, x) & 0x03030303u;
+    x = shl_or<3>(x, x) & 0x11111111u;
     return x;
+}
+
+// LDS table: entry (key << 4) | sum, key = 2 n + b, holds A = -E as a
+// 64-bit value (x = low word, y = high word), so that the high word of
+// u + A is -[u < E].  256 entries: every byte a corrupted cell could form
+// stays in bounds (entries that no spin state reaches reject).
+struct BCLds {
+    uint2 e[256];
+};
+
+__device__ __forceinline__ uint2 bc_addend(uint32_t thr, bool always)
+{
+    const uint64_t E = always ? (uint64_t(1) << 32) : (uint64_t)thr;
+    const uint64_t A = uint64_t(0) - E;
+    return make_uint2((uint32_t)A, (uint32_t)(A >> 32));
+}
+
+__device__ __forceinline__ void load_bc_table(BCLds& lds, const BCTable& tbl)
+{
+    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x) {
+        const uint32_t key = i >> 4, sj = i & 15u;
+        uint2 v = make_uint2(0u, 0u);
+        if (key < 6u && sj < 9u) {
+            const uint32_t idx = key * 9u + sj;               // ((n * 2 + b) * 9 + sum)
+            v = bc_addend(tbl.thr[idx], tbl.always[idx] != 0);
+        }
+        lds.e[i] = v;
+    }
+    __syncthreads();
+}
+
+// The same from a 96-entry (thr, always) table indexed key * 16 + sum.
+__device__ __forceinline__ void load_bc_table(BCLds& lds, const uint2* __restrict__ src96)
+{
+    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x) {
+        uint2 v = make_uint2(0u, 0u);
+        if (i < 96u) {
+            const uint2 e = src96[i];
+            if ((i >> 4) < 6u && (i & 15u) < 9u) v = bc_addend(e.x, e.y != 0);
+        }
+        lds.e[i] = v;
+    }
+    __syncthreads();
 }
 
 template <bool HI0>
@@ -123,18 +167,21 @@ __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const
                                         uint32_t halo, bool odd, uint64_t blk0, uint32_t pbits, uint32_t t,
                                         uint32_t color, uint32_t k0, uint32_t k1, const uint2* __restrict__ tab)
 {
-    uint32_t key[4], sum[4], nxt[4];
+    uint32_t ev[4], od[4], nxt[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const uint32_t s = pick(src, d);
         const uint32_t b = spread8(pbits >> (8 * d));
-        sum[d] = pick(up, d) + pick(dn, d) + pick(mid, d) + horizontal(mid, d, halo, odd);
-        key[d] = s + s + b;                                   // n * 2 + b, at most 5 per nibble
+        const uint32_t sum = pick(up, d) + pick(dn, d) + pick(mid, d) + horizontal(mid, d, halo, odd);
+        const uint32_t key = s + s + b;                       // n * 2 + b, at most 5 per nibble
+        ev[d] = ((key & 0x0F0F0F0Fu) << 4) | (sum & 0x0F0F0F0Fu);     // cells 0, 2, 4, 6 as bytes
+        od[d] = (key & 0xF0F0F0F0u) | ((sum >> 4) & 0x0F0F0F0Fu);    // cells 1, 3, 5, 7
         const uint32_t v = s + 0x11111111u + b;               // n + 1 + b in 1..4
         const uint32_t ge3 = ((v + 0x55555555u) & 0x88888888u) >> 3;
-        nxt[d] = v - (ge3 | (ge3 << 1));                      // mod 3
+        nxt[d] = v - shl_or<1>(ge3, ge3);                     // mod 3
     }
-    uint32_t acc = 0;
+    // nacc = -(accept bits), shifted in cell by cell: 2 (-a) - bit = -(2 a + bit)
+    uint32_t nacc = 0;
 #pragma unroll
     for (int h = 1; h >= 0; --h) {
         Philox4 P[4];
@@ -148,48 +195,22 @@ __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const
 #pragma unroll
             for (int d = 3; d >= 0; --d) {
                 const int j = 4 * h + jj;
-                const uint32_t kj = (key[d] >> (4 * j)) & 0xFu;
-                const uint32_t sj = (sum[d] >> (4 * j)) & 0xFu;
-                uint32_t idx = kj * 16u + sj;
-                idx = idx < 95u ? idx : 95u;
+                const uint32_t idx = (((j & 1) ? od[d] : ev[d]) >> (8 * (j >> 1))) & 0xFFu;
                 const uint2 e = tab[idx];
                 const uint32_t u = philox_word(P[d], jj);
-                const uint64_t lhs = (uint64_t)u;
-                const uint64_t rhs = ((uint64_t)e.y << 32) | e.x;
-                acc = acc + acc + (uint32_t)(lhs < rhs);
+                nacc = shl_add<1>(nacc, add_hi(u, ((uint64_t)e.y << 32) | e.x));
             }
     }
+    const uint32_t acc = 0u - nacc;
     uint32_t res[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const uint32_t s = pick(src, d);
         const uint32_t a = (acc >> d) & 0x11111111u;
-        const uint32_t mask = (a << 4) - a;                   // 0xF in accepted nibbles
+        const uint32_t mask = shl_opaque<4>(a) - a;           // 0xF in accepted nibbles
         res[d] = (s & ~mask) | (nxt[d] & mask);
     }
     return make_uint4(res[0], res[1], res[2], res[3]);
-}
-
-// Blume-Capel table in LDS, 96 entries indexed (n * 2 + b) * 16 + cell-sum:
-// x = threshold, y = 1 when dE <= 0 (always accept).  Unused slots (sum > 8,
-// n > 2) never accept.
-struct BCLds {
-    uint2 e[96];
-};
-
-__device__ __forceinline__ void load_bc_table(BCLds& lds, const BCTable& tbl)
-{
-    for (uint32_t i = threadIdx.x; i < 96u; i += blockDim.x) {
-        const uint32_t key = i >> 4, sj = i & 15u;
-        uint2 v = make_uint2(0u, 0u);
-        if (key < 6u && sj < 9u) {
-            const uint32_t n = key >> 1, b = key & 1u;
-            const uint32_t idx = (n * 2u + b) * 9u + sj;
-            v = make_uint2(tbl.thr[idx], tbl.always[idx] ? 1u : 0u);
-        }
-        lds.e[i] = v;
-    }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -303,10 +324,11 @@ __device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t s
     return w;
 }
 
-// Bucketed lookup.  Bucket b = u >> 20 (4096 buckets) holds (Tn, kw) with
-// max{k : T[k] <= u} = kw + [u >= Tn] for every u of the bucket; buckets
-// where no such pair exists (two or more thresholds inside) have bit 31 of
-// kw set, and a word with any such draw takes the exact search instead.
+// Bucketed lookup.  Bucket b = u >> 20 (4096 buckets) holds a 64-bit
+// addend A = kw 2^32 + 2^32 - Tn with max{k : T[k] <= u} = kw + [u >= Tn] =
+// the high word of u + A for every u of the bucket.  Buckets where no such
+// pair exists (two or more thresholds inside) hold A = 2^63, and a word
+// with any such draw takes the exact search instead.
 constexpr int kLutBuckets = 4096;
 
 template <bool HI0>
@@ -323,8 +345,9 @@ __device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint3
         for (int j = 0; j < 4; ++j) {
             const uint32_t u = philox_word(P, j);
             const uint2 e = B[u >> 20];
-            flags |= e.y;
-            w |= (e.y + (u >= e.x ? 1u : 0u)) << (4 * (4 * h + j));
+            const uint32_t k = add_hi(u, ((uint64_t)e.y << 32) | e.x);
+            flags |= k;
+            w |= k << (4 * (4 * h + j));
         }
     }
     if (flags >> 31) w = lut_word<HI0>(g0, t, stream, k0, k1, T, T8, kmax);
