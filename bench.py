@@ -67,10 +67,11 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(L):
-    """HBM bytes per half-sweep launch from the committed PMC summary, if it
-    was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_ising_half_sweep_L%d.json" % L)
+def profile_record(name):
+    """PMC figures of a sweep kernel ("ising_4bit", "blume_capel_4bit",
+    "ising_1bit") from the committed summary, if they were taken on the
+    current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_sweep_kernels.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -78,7 +79,19 @@ def measured_traffic(L):
         return None
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("sweep_kernels", {}).get(name)
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed PMC summary (or None)."""
+    k = profile_record(name)
+    return None if k is None else round(k["hbm_bytes_per_launch"])
+
+
+def measured_valu_busy(name):
+    """Fraction of SIMD cycles issuing VALU instructions (PMC), or None."""
+    k = profile_record(name)
+    return None if k is None or "valu_busy" not in k else round(k["valu_busy"], 3)
 
 
 def attainable_copy():
@@ -112,7 +125,7 @@ def replica_set(n=512, seed=3):
     return out
 
 
-def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label):
+def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label, traffic_key):
     """One lattice quenched from its random start and relaxed for n sweeps,
     with B/M/Q and protocol C(r,t) at t = 2^k; whole-job and sweep-only
     rates, the average half-sweep and its HBM and Philox fractions."""
@@ -157,6 +170,9 @@ def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label)
            "avg_half_sweep_ms": round(sweep_ms / (2 * n), 4),
            "hbm_frac": round(half_bytes / half_s / 1e9 / HBM_PEAK_GBS, 4),
            "philox_frac": round(gblocks / PHILOX_PEAK_GBLOCKS, 4),
+           "hbm_traffic_bytes_per_launch": measured_traffic(traffic_key),
+           "valu_busy_pmc": measured_valu_busy(traffic_key),
+           "algorithmic_bytes_per_launch": half_bytes,
            "measure_share": round(t_meas / wall, 4),
            "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"],
                      "schwinger_dyson": round(mcl.schwinger_dyson(out["sd"], beta), 7)}}
@@ -172,7 +188,7 @@ def run_blume_capel(args):
     # one u32 acceptance draw plus one proposal bit per update
     res = quench_leg(mcl.BC, L, 1003, 1 / 1.4, 1.0, n, 3.0 * L * L / 4.0, 0.25 + 1.0 / 128,
                      "Blume-Capel quench, L=2^16, T=1.4, D=1.0, random start, %d sweeps, protocol C(r,t) and "
-                     "B/M/Q at t=2^k" % n)
+                     "B/M/Q at t=2^k" % n, "blume_capel_4bit")
     res["paper_context_updates_per_ns"] = 941
     return res
 
@@ -186,7 +202,7 @@ def run_ising_1bit(args):
     # of 4 sites (exp4 and exp8 bits) = 1/8 Philox block per update
     res = quench_leg(mcl.ISING_LUT, L, 1002, BETA_C, 0.0, n, 3.0 * L * L / 16.0, 1.0 / 8,
                      "Ising 1-bit (table-driven random bits), L=2^17, T=T_c, random start, %d sweeps, protocol "
-                     "C(r,t) and B/M at t=2^k" % n)
+                     "C(r,t) and B/M at t=2^k" % n, "ising_1bit")
     res["paper_context_updates_per_ns"] = 1797
     return res
 
@@ -312,7 +328,7 @@ def run(args):
     half_bytes = 3.0 * L * L / 4.0                 # read P_c, read P_{1-c}, write P_c (4-bit cells)
     hbm_gbs = half_bytes / (half_ms * 1e-3) / 1e9
     blocks_gps = half_updates / 4.0 / (half_ms * 1e-3) / 1e9   # one 32-bit draw per update
-    traffic = measured_traffic(L)
+    traffic = measured_traffic("ising_4bit") if L == 2 ** 17 else None
     res = {
         "metric": METRIC,
         "value": round(updates / (wall * 1e9), 2),
@@ -340,7 +356,8 @@ def run(args):
                      "kernel": "half_sweep_kernel<Ising>", "avg_launch_ms": round(half_ms, 4),
                      "work_per_launch": "%d Philox4x32-10 blocks (one u32 draw per update), %d bytes" % (
                          int(half_updates / 4), int(half_bytes)),
-                     "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)},
+                     "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                     "valu_busy_pmc": measured_valu_busy("ising_4bit") if L == 2 ** 17 else None},
         "paper_context": {"updates_per_ns": 1797, "hardware": "1x GB200, 1-bit cells with LUT random bits",
                           "note": "context only"},
         "measures": measures,
@@ -356,6 +373,8 @@ def main():
     ap.add_argument("--L", type=int, default=2 ** 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
+    ap.add_argument("--extras", default="bc,lut,batched,serving",
+                    help="comma list of the further legs: bc, lut, batched, serving")
     ap.add_argument("--bc-sweeps", type=int, default=2000)
     ap.add_argument("--lut-sweeps", type=int, default=2000)
     ap.add_argument("--replicas", type=int, default=512)
@@ -367,14 +386,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     res = run(args)
-    if not args.no_extras:
+    extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]
+    if "bc" in extras:
         log("bench: Blume-Capel L=2^16")
         res["blume_capel"] = run_blume_capel(args)
+    if "lut" in extras:
         log("bench: Ising 1-bit L=2^17")
         res["ising_1bit"] = run_ising_1bit(args)
+    if "batched" in extras:
         log("bench: batched vs plain")
         res["batched"] = run_batched(args)
         res["batched_over_plain"] = res["batched"]["batched_over_plain"]
+    if "serving" in extras:
         log("bench: serving")
         res["serving"] = run_serving(args)
     if not args.no_cpu_baseline:

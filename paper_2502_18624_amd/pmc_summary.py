@@ -4,7 +4,11 @@ FETCH_SIZE and WRITE_SIZE are scaled by what the same counters read for the
 calibration copy kernel, which moves a known 4 GiB in and 4 GiB out per
 dispatch.  Usage (from the repository root, after the four PMC runs):
 
-    python -m paper_2502_18624_amd.pmc_summary <dir with fetch/ write/ cfetch/ cwrite/> <L>
+    python -m paper_2502_18624_amd.pmc_summary <dir with fetch/ write/ cfetch/ cwrite/> [<dir with valu/>]
+
+The optional second directory holds a run with the VALU and LDS counters
+(SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES
+SQ_BUSY_CYCLES GRBM_GUI_ACTIVE).
 """
 from __future__ import annotations
 
@@ -41,24 +45,75 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def main(d, L):
+# The three sweep kernels of the benchmark: name prefix, lattice side, and
+# algorithmic bytes per launch (read the own plane, read the other plane,
+# write the own plane: 3 L^2 / 2 cells x bits / 8).
+SWEEP_KERNELS = {
+    "ising_4bit": ("half_sweep_kernel<0, ", 2 ** 17, 4),
+    "blume_capel_4bit": ("half_sweep_kernel<1, ", 2 ** 16, 4),
+    "ising_1bit": ("lut_half_kernel<", 2 ** 17, 1),
+}
+
+
+# MI355X: 8 XCDs of 32 CUs, 4 SIMDs of 16 lanes per CU; a wave64 VALU
+# instruction occupies its SIMD for 4 cycles.  GRBM_GUI_ACTIVE is summed
+# over the XCDs.
+N_XCD, N_CU, N_SIMD = 8, 256, 1024
+
+
+def per_kernel_counters(path):
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        d[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in d.items()}
+
+
+def valu_summary(path):
+    """VALU issue and LDS figures per sweep kernel from a run with SQ_INSTS_VALU,
+    SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES and GRBM_GUI_ACTIVE."""
+    c = per_kernel_counters(path)
+    out = {}
+    for name, (prefix, L, bits) in SWEEP_KERNELS.items():
+        ks = [k for k in c if k.startswith(prefix)]
+        if not ks:
+            continue
+        m = {n: sum(c[k][n] for k in ks) / len(ks) for n in c[ks[0]]}
+        cycles = m["GRBM_GUI_ACTIVE"] / N_XCD
+        updates = L * L / 2
+        out[name] = {"valu_wave_insts_per_launch": m["SQ_INSTS_VALU"],
+                     "valu_lane_ops_per_update": m["SQ_INSTS_VALU"] * 64 / updates,
+                     "valu_busy": m["SQ_INSTS_VALU"] * 4 / (N_SIMD * cycles),
+                     "gpu_cycles_per_launch": cycles,
+                     "lds_insts_per_launch": m["SQ_INSTS_LDS"],
+                     "lds_bank_conflict_share": m["SQ_LDS_BANK_CONFLICT"] / N_CU / cycles,
+                     "waves": m["SQ_WAVES"]}
+    return out
+
+
+def main(d, valu_dir=None):
     f = per_kernel(os.path.join(d, "fetch", "bench_counter_collection.csv"))
     w = per_kernel(os.path.join(d, "write", "bench_counter_collection.csv"))
     cf = per_kernel(os.path.join(d, "cfetch", "copy_counter_collection.csv"))
     cw = per_kernel(os.path.join(d, "cwrite", "copy_counter_collection.csv"))
     copy_kib = 4 * 1024 * 1024
     fs, ws = copy_kib / cf["copy_kernel"], copy_kib / cw["copy_kernel"]
-    hs = [k for k in f if k.startswith("half_sweep_kernel<0, true")]
-    fetch = sum(f[k] for k in hs) / len(hs) * fs * 1024
-    write = sum(w[k] for k in hs) / len(hs) * ws * 1024
-    alg = 3 * L * L / 4
-    rec = {"kernel": "half_sweep_kernel<Ising> (mean of both colours)", "L": L, "kernel_source_sha": source_sha(),
-           "fetch_scale": fs, "write_scale": ws, "hbm_read_bytes_per_launch": fetch,
-           "hbm_write_bytes_per_launch": write, "hbm_bytes_per_launch": fetch + write,
-           "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (fetch + write) / alg,
-           "per_kernel_bytes": {k: [f[k] * fs * 1024, w.get(k, 0.0) * ws * 1024] for k in f}}
-    return rec
+    kernels = {}
+    for name, (prefix, L, bits) in SWEEP_KERNELS.items():
+        hs = [k for k in f if k.startswith(prefix)]
+        if not hs:
+            continue
+        fetch = sum(f[k] for k in hs) / len(hs) * fs * 1024
+        write = sum(w.get(k, 0.0) for k in hs) / len(hs) * ws * 1024
+        alg = 3 * L * L * bits / 8 / 2
+        kernels[name] = {"kernels": hs, "L": L, "bits_per_cell": bits, "hbm_read_bytes_per_launch": fetch,
+                         "hbm_write_bytes_per_launch": write, "hbm_bytes_per_launch": fetch + write,
+                         "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (fetch + write) / alg}
+    if valu_dir:
+        for name, v in valu_summary(os.path.join(valu_dir, "valu", "bench_counter_collection.csv")).items():
+            kernels.setdefault(name, {}).update(v)
+    return {"kernel_source_sha": source_sha(), "fetch_scale": fs, "write_scale": ws, "sweep_kernels": kernels,
+            "per_kernel_bytes": {k: [f[k] * fs * 1024, w.get(k, 0.0) * ws * 1024] for k in f}}
 
 
 if __name__ == "__main__":
-    print(json.dumps(main(sys.argv[1], int(sys.argv[2])), indent=1))
+    print(json.dumps(main(sys.argv[1], sys.argv[2] if len(sys.argv) > 2 else None), indent=1))
