@@ -301,8 +301,10 @@ static int64_t update_site(int8_t* s, int model, int64_t L, uint64_t seed, uint3
     *dq = 0;
 
     if (model == ORA_ISING_LUT) {
-        /* section 3.2: exp4 = random bits, exp8 = random bits & exp4;
-         * flip = (eq4 & exp8) | (eq3 & exp4) | (~eq4 & ~eq3) */
+        /* section 3.2: a spin with at most two aligned neighbours flips; with
+         * three it flips when its stream-0 bit (probability p = e^{-4 beta}) is
+         * set; with four when both its stream-0 and stream-1 bits are set
+         * (probability p^2 = e^{-8 beta}). */
         int aligned = (nb[0] == sv) + (nb[1] == sv) + (nb[2] == sv) + (nb[3] == sv);
         int flip;
         if (aligned <= 2) {

@@ -291,8 +291,8 @@ __device__ __forceinline__ void band_update(uint32_t* __restrict__ own, const ui
 //   b_n = neighbour word ^ own word marks the misaligned neighbours; with
 //   half adders over the four b_n, eq4 = no mismatch and eq3 = exactly one;
 //   exp4 = the 4-bit patterns of 8 table draws (stream 0), exp8 = those of
-//   stream 1 ANDed with exp4; flip = (eq4 & exp8) | (eq3 & exp4) |
-//   ~(eq4 | eq3).
+//   stream 1 ANDed with exp4 (probability e^{-8 beta}); a cell keeps its
+//   value iff eq4 with no exp8 bit or eq3 with no exp4 bit, all others flip.
 // Table search: T is the 16-entry table clamped to 2^32 - 1 (in LDS), kmax
 // the last entry that was below 2^32; the pattern is min(k, kmax) with k
 // the largest index whose clamped entry is <= u, which equals the largest
@@ -374,8 +374,10 @@ __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, cons
         const uint64_t g0 = (kv + 32u * d) >> 2;
         const uint32_t e4 = lut_word_fast<HI0>(g0, t, 8u + 2u * color, k0, k1, B, T, T8, kmax);
         const uint32_t e8 = lut_word_fast<HI0>(g0, t, 9u + 2u * color, k0, k1, B, T, T8, kmax) & e4;
-        const uint32_t flip = (eq4 & e8) | (eq3 & e4) | ~(eq4 | eq3);
-        res[d] = s ^ flip;
+        // a spin keeps its value only when four neighbours agree and its
+        // e^{-8 beta} bit is clear, or three agree and its e^{-4 beta} bit is clear
+        const uint32_t keep = (eq4 & ~e8) | (eq3 & ~e4);
+        res[d] = ~(s ^ keep);
     }
     return make_uint4(res[0], res[1], res[2], res[3]);
 }
