@@ -266,67 +266,77 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// a7, every source, r = 0..R (R <= 32): LDS tile of SW columns (+1 halo
-// column on the right for x-partners) by TH source rows (+32 halo rows
-// below for y-partners), both planes.  Thread (j, g) handles column j and
-// rows 4g .. 4g + 3 of the tile, for r in [RLO, RHI].
+// a7, every source, r = 0..R (R <= 32): LDS tile of SW words (+1 halo word
+// on the right for x-partners) by TH source rows (+32 halo rows below for
+// y-partners), both planes, with the cells as 1-bit words of 32 cells: the
+// sign bit for Ising, and for Blume-Capel a second word of nonzero bits.  A
+// 4-bit row vector (32 cells) packs into one word, a 1-bit plane word is
+// stored as it is, so every model has L / 64 words per tile row.  Thread
+// (j, g) handles word column j and rows 4g .. 4g + 3 of the tile, for r in
+// [RLO, RHI]: per distance, axis and 32 pairs one funnel shift (x only),
+// an xor (and two ands for Blume-Capel) and the bit counts.
 // ---------------------------------------------------------------------------
 constexpr int kSW = 32;
 constexpr int kTH = 32;
 constexpr int kHalo = 32;
 constexpr int kTileRows = kTH + kHalo;
 
+template <int MODEL>
 struct ShortTile {
-    uint4 v[2][kTileRows][kSW + 1];
+    static constexpr int NB = MODEL == 1 ? 2 : 1;   // bit planes: sign [, nonzero]
+    uint32_t v[2][NB][kTileRows][kSW + 1];
 };
 
-// Adds s * s' summed over the cell pairs of two words to acc, except for
-// the Ising models, where every product is nonzero and acc counts the pairs
-// of opposite sign (the sum is then pairs - 2 acc).
-template <int MODEL>
-__device__ __forceinline__ void pair_acc(uint32_t a, uint32_t b, int& acc)
+// Bit `BIT` of each nibble of the 4 words (32 cells), in cell order.
+template <int BIT>
+__device__ __forceinline__ uint32_t nibble_bits(const uint4& v, bool invert)
 {
-    if (MODEL == 2) {
-        acc += (int)popc(a ^ b);                  // 1-bit cells: pairs of opposite sign
-    } else if (MODEL == 0) {
-        acc += (int)popc((a ^ b) & 0x22222222u);
-    } else {
-        const uint32_t z = ~(a | b) & 0x11111111u;
-        acc += (int)popc(z) - 2 * (int)popc(((a ^ b) >> 1) & z);
+    uint32_t r = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint32_t x = ((invert ? ~pick(v, d) : pick(v, d)) >> BIT) & 0x11111111u;
+        x = (x | (x >> 3)) & 0x03030303u;
+        x = (x | (x >> 6)) & 0x000F000Fu;
+        x = (x | (x >> 12)) & 0x000000FFu;
+        r |= x << (8 * d);
     }
+    return r;
 }
 
 template <int MODEL, int RLO, int RHI, int C, int PAR>
-__device__ __forceinline__ void short_row(const ShortTile& T, int lr, int j, int (&ax)[33], int (&ay)[33])
+__device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int j, int (&ax)[33], int (&ay)[33])
 {
-    const uint4 v = T.v[C][lr][j];
-    uint32_t w[2][7];
+    const uint32_t o = T.v[C][0][lr][j];
+    const uint32_t oz = MODEL == 1 ? T.v[C][1][lr][j] : 0u;
+    uint32_t w0[2], w1[2], z0[2], z1[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        const uint4 a = T.v[p][lr][j], b = T.v[p][lr][j + 1];
-        w[p][0] = a.x; w[p][1] = a.y; w[p][2] = a.z; w[p][3] = a.w;
-        w[p][4] = b.x; w[p][5] = b.y; w[p][6] = b.z;
+        w0[p] = T.v[p][0][lr][j];
+        w1[p] = T.v[p][0][lr][j + 1];
+        z0[p] = MODEL == 1 ? T.v[p][ShortTile<MODEL>::NB - 1][lr][j] : 0u;
+        z1[p] = MODEL == 1 ? T.v[p][ShortTile<MODEL>::NB - 1][lr][j + 1] : 0u;
     }
 #pragma unroll
     for (int r = RLO; r <= RHI; ++r) {
         const int pc = C ^ (r & 1);
-        const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);
-        const int mb = m * (MODEL == 2 ? 1 : 4);         // shift in bits
-        const uint4 py = T.v[pc][lr + r][j];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const uint32_t o = pick(v, d);
-            const int base = d + (mb >> 5);
-            const uint32_t px = (mb & 31) ? funnel(w[pc][base + 1], w[pc][base], mb & 31) : w[pc][base];
-            pair_acc<MODEL>(o, px, ax[r]);
-            pair_acc<MODEL>(o, pick(py, d), ay[r]);
+        const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);     // in-plane shift, 0..16
+        const uint32_t px = m ? funnel(w1[pc], w0[pc], m) : w0[pc];
+        const uint32_t py = T.v[pc][0][lr + r][j];
+        if (MODEL != 1) {
+            ax[r] += (int)popc(o ^ px);                 // pairs of opposite sign
+            ay[r] += (int)popc(o ^ py);
+        } else {
+            const uint32_t zx = (m ? funnel(z1[pc], z0[pc], m) : z0[pc]) & oz;
+            const uint32_t zy = T.v[pc][ShortTile<MODEL>::NB - 1][lr + r][j] & oz;
+            ax[r] += (int)popc(zx) - 2 * (int)popc(zx & (o ^ px));
+            ay[r] += (int)popc(zy) - 2 * (int)popc(zy & (o ^ py));
         }
     }
 }
 
 // Distances [RLO, RHI] over the thread's 4 rows of the current tile.
 template <int MODEL, int RLO, int RHI>
-__device__ __forceinline__ void short_chunk(const ShortTile& T, int j, int g, int (&ax)[33], int (&ay)[33])
+__device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, int g, int (&ax)[33], int (&ay)[33])
 {
     // tile rows 4g .. 4g + 3; the tile's first row is even, so the parity of
     // y + c is that of the local row + c
@@ -339,19 +349,19 @@ __device__ __forceinline__ void short_chunk(const ShortTile& T, int j, int g, in
     }
 }
 
-// Persistent over tiles: each workgroup loads tiles (strip of kSW columns by
+// Persistent over tiles: each workgroup loads tiles (strip of kSW words by
 // kTH rows, both planes, with halos) in turn and keeps its per-distance sums
 // in registers; one atomic per value per workgroup at the end.
 template <int MODEL>
 __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restrict__ planes, uint32_t L, int R,
                                                          int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
 {
-    __shared__ ShortTile T;
+    __shared__ ShortTile<MODEL> T;
     __shared__ int64_t red[4][66];
-    const uint32_t Q = L >> (MODEL == 2 ? 8 : 6);
-    const uint32_t nstrips = (Q + kSW - 1) / kSW;
+    const uint32_t Wp = L >> 6;                     // tile words per row, every model
+    const uint32_t nstrips = (Wp + kSW - 1) / kSW;
     const uint32_t ntiles = nstrips * (L / kTH);
-    const size_t plane_vecs = (size_t)L * Q;
+    const size_t plane_units = (size_t)L * Wp;      // 16-byte vectors (4-bit) or words (1-bit) per plane
     const uint4* P4 = reinterpret_cast<const uint4*>(planes);
     const int j = threadIdx.x & (kSW - 1);
     const int g = threadIdx.x / kSW;
@@ -371,15 +381,22 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             uint32_t y = y0 + row;
             while (y >= L) y -= L;
             uint32_t qq = q0 + col;
-            while (qq >= Q) qq -= Q;
-            T.v[c][row][col] = P4[c * plane_vecs + (size_t)y * Q + qq];
+            while (qq >= Wp) qq -= Wp;
+            const size_t at = c * plane_units + (size_t)y * Wp + qq;
+            if (MODEL == 2) {
+                T.v[c][0][row][col] = planes[at];
+            } else {
+                const uint4 v = P4[at];
+                T.v[c][0][row][col] = nibble_bits<1>(v, false);            // n = 2: s = +1
+                if (MODEL == 1) T.v[c][ShortTile<MODEL>::NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+            }
         }
         __syncthreads();
-        if (q0 + (uint32_t)j < Q) {
+        if (q0 + (uint32_t)j < Wp) {
             short_chunk<MODEL, 0, 10>(T, j, g, ax, ay);
             if (R > 10) short_chunk<MODEL, 11, 21>(T, j, g, ax, ay);
             if (R > 21) short_chunk<MODEL, 22, 32>(T, j, g, ax, ay);
-            pairs += MODEL == 2 ? 1024 : 256;     // 4 rows x 2 planes x cells of a vector, per distance
+            pairs += 256;          // 4 rows x 2 planes x 32 cells, per distance
         }
     }
     int64_t v[66];
@@ -675,8 +692,8 @@ hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s)
 hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s)
 {
     if (R < 0) return hipSuccess;
-    const uint32_t Q = (uint32_t)g.Q;
-    const uint32_t nstrips = (Q + kSW - 1) / kSW;
+    const uint32_t Wp = (uint32_t)(g.L >> 6);
+    const uint32_t nstrips = (Wp + kSW - 1) / kSW;
     const uint32_t ntiles = nstrips * (uint32_t)(g.L / kTH);
     const dim3 grid(std::min<uint32_t>(ntiles, 1024));
     const uint32_t L = (uint32_t)g.L;
