@@ -576,6 +576,67 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
         if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
 }
 
+// Along x with the row in LDS (L a power of two, L bytes fit): the row is
+// stored residue by residue, R_rho[a] = s(16 a + rho, y) (P = L / 16 bytes
+// each), so the partners of the sources 16 a, a = 4 q .. 4 q + 3, at
+// distance r are the bytes R_{r mod 16}[4 q + (r >> 4) ...], one
+// v_alignbyte_b32 of two LDS words, and the four products are one v_dot4.
+// Wave w owns the distances k = w, w + 16, ... of the launch and sweeps all
+// sources of the row for each, so it reduces once per distance and row.
+template <int CB>
+__global__ __launch_bounds__(1024) void corr_sx_dot4_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                           const int32_t* __restrict__ rlist, int nr,
+                                                           int64_t* __restrict__ Cx)
+{
+    extern __shared__ int sx_lds[];                 // nr int32 sums, then the row
+    int* sums = sx_lds;
+    int8_t* srow = reinterpret_cast<int8_t*>(sx_lds + nr);
+    const uint32_t* srow_w = reinterpret_cast<const uint32_t*>(srow);
+    const uint32_t W = L >> Cell<CB>::kWordShift;
+    const uint32_t P = L >> 4;                      // bytes per residue class
+    const uint32_t PQ = P >> 2;                     // words per residue class (a power of two)
+    const size_t plane_words = (size_t)L * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwaves = blockDim.x >> 6;
+    for (int k = threadIdx.x; k < nr; k += blockDim.x) sums[k] = 0;
+    for (uint32_t b = blockIdx.x; b < (L >> 4); b += gridDim.x) {
+        const uint32_t y = 16 * b;
+        __syncthreads();
+        for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+            const uint32_t c = idx >= W ? 1u : 0u;
+            const uint32_t wd = idx - c * W;
+            const uint32_t word = planes[c * plane_words + (size_t)y * W + wd];
+            const uint32_t par = (y + c) & 1u;              // x = 2 i + par
+#pragma unroll
+            for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
+                const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
+                const int sv = CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1 : (((word >> k) & 1u) ? 1 : -1);
+                srow[(x & 15) * P + (x >> 4)] = (int8_t)sv;
+            }
+        }
+        __syncthreads();
+        for (int k = wave; k < nr; k += nwaves) {
+            const uint32_t r = (uint32_t)rlist[k];
+            const uint32_t base = (r & 15u) * PQ;
+            const uint32_t sh = r >> 4;                     // whole sources of offset
+            const uint32_t qs = sh >> 2, bs = sh & 3u;
+            int acc = 0;
+            for (uint32_t q = lane; q < PQ; q += 64) {
+                const uint32_t wi = (q + qs) & (PQ - 1);
+                const uint32_t lo = srow_w[base + wi];
+                const uint32_t hi = srow_w[base + ((wi + 1) & (PQ - 1))];
+                const uint32_t part = __builtin_amdgcn_alignbyte(hi, lo, bs);
+                acc = __builtin_amdgcn_sdot4((int)srow_w[q], (int)part, acc, false);
+            }
+            const int s2 = wave_sum_i32(acc);
+            if (lane == 0) sums[k] += s2;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nr; k += blockDim.x)
+        if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
+}
+
 // Along y, target-row order: block (residue rho, list chunk, band of rows,
 // source chunk).  Target row y' = rho + 16 k pairs with source row
 // b = (y' - r) / 16 for every sampled r = rho (mod 16); the positions of
@@ -740,14 +801,21 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
         const size_t lds_sums = (size_t)nr * 4;
         const bool use_lds = lds_sums + L <= 160u * 1024u;
         const size_t lds = lds_sums + (use_lds ? L : 0);
-        static size_t attr_bytes[2] = {0, 0};
-        const void* fn = use_lds ? (const void*)corr_sx_kernel<CB, true> : (const void*)corr_sx_kernel<CB, false>;
-        if (lds > 64u * 1024u && attr_bytes[use_lds] < lds) {
+        // the dot4 form needs whole words per residue class and a power-of-two row
+        const bool dot4 = use_lds && (L & (L - 1)) == 0 && L >= 64;
+        static size_t attr_bytes[3] = {0, 0, 0};
+        const int fi = dot4 ? 2 : (use_lds ? 1 : 0);
+        const void* fn = dot4 ? (const void*)corr_sx_dot4_kernel<CB>
+                              : (use_lds ? (const void*)corr_sx_kernel<CB, true> : (const void*)corr_sx_kernel<CB, false>);
+        if (lds > 64u * 1024u && attr_bytes[fi] < lds) {
             e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            attr_bytes[use_lds] = lds;
+            attr_bytes[fi] = lds;
         }
-        if (use_lds)
+        if (dot4)
+            hipLaunchKernelGGL((corr_sx_dot4_kernel<CB>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
+                               a.Cx + j0);
+        else if (use_lds)
             hipLaunchKernelGGL((corr_sx_kernel<CB, true>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
                                a.Cx + j0);
         else
