@@ -622,7 +622,7 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         MCL_HIP(mcl::launch_zero(h->Cx, nr, h->stream));
         MCL_HIP(mcl::launch_zero(h->Cy, nr, h->stream));
     }
-    MCL_HIP(mcl::launch_bmq(h->g, h->acc, h->stream));
+    MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, h->stream));
     // The host buffer of residue lists must outlive the asynchronous copy:
     // it lives until the synchronisation below.
     std::vector<int32_t> res;

@@ -47,7 +47,7 @@ hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 // (corrupted) are L^2 minus the three counts.
 constexpr int kAccSlots = 16;
 hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s);
-hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s);
+hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s);
 // Correlations from every source at r = 0..R (R <= 32), LDS-tiled.
 hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s);
 // Correlations from every source at distances r[0..nr) (any r <= L/2).

@@ -163,8 +163,9 @@ __device__ __forceinline__ void block_add_xy(const int64_t (&v)[2 * N], int64_t*
 __device__ __forceinline__ void sd_add4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t (&hist)[9])
 {
     const uint32_t S = a + b + c + d;
-    const uint32_t m2 = ((o >> 1) & 0x11111111u) * 15u;             // sigma = +1
-    const uint32_t m0 = (~(o | (o >> 1)) & 0x11111111u) * 15u;      // sigma = -1
+    const uint32_t e2 = (o >> 1) & 0x11111111u, e0 = ~(o | (o >> 1)) & 0x11111111u;
+    const uint32_t m2 = shl_opaque<4>(e2) - e2;                    // 0xF where sigma = +1
+    const uint32_t m0 = shl_opaque<4>(e0) - e0;                    // 0xF where sigma = -1
     const uint32_t t = (S & m2) | ((0x88888888u - S) & m0) | (0x44444444u & ~(m0 | m2));
     const uint32_t b0 = t & 0x11111111u, b1 = (t >> 1) & 0x11111111u;
     const uint32_t b2 = (t >> 2) & 0x11111111u, b3 = (t >> 3) & 0x11111111u;
@@ -194,15 +195,34 @@ __device__ __forceinline__ void sd_add1(uint32_t o, uint32_t a, uint32_t b, uint
     hist[4] += 32u - c8 - c0 - c6 - c2;
 }
 
+// 4-bit Ising cells (n in {0, 2}): per nibble the number d of neighbours
+// of the opposite sign, 0..4 (each xor nibble is 0 or 2, their sum at most
+// 8, and bit 0 of every nibble stays clear, so the shift moves nothing
+// across nibbles).  Adds the histogram of t = sigma h + 4 = 8 - 2 d and
+// returns the sum of d over the 8 cells.
+__device__ __forceinline__ uint32_t sd_add_ising4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                                  uint32_t (&hist)[9])
+{
+    const uint32_t D = ((a ^ o) + (b ^ o) + (c ^ o) + (d ^ o)) >> 1;
+    const uint32_t p0 = D & 0x11111111u, p1 = (D >> 1) & 0x11111111u, p2 = (D >> 2) & 0x11111111u;
+    hist[8] += popc(~(p0 | p1 | p2) & 0x11111111u);   // d = 0
+    hist[6] += popc(p0 & ~p1);                          // d = 1
+    hist[4] += popc(p1 & ~p0);                          // d = 2
+    hist[2] += popc(p0 & p1);                           // d = 3
+    hist[0] += popc(p2);                                // d = 4
+    return popc(p0) + 2u * popc(p1) + 4u * popc(p2);
+}
+
 // One pass over both planes: B and M, Q and the value counts, and the
 // Schwinger-Dyson histogram (section 4) of sigma h over every site.  A task
 // is a column vector q of a band of rows; the thread keeps rows y - 1, y,
 // y + 1 of both planes.  Colour-0 sites carry the bonds (each bond has one
 // colour-0 end); both colours add to the counts and the histogram.
-template <int CB>
+template <int MODEL>
 __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
                                                   uint32_t L, uint32_t rows, int64_t* __restrict__ acc)
 {
+    constexpr int CB = MODEL == 2 ? 1 : 4;
     using C = Cell<CB>;
     __shared__ int64_t red[4][14];
     const uint32_t Q = L >> C::kVecShift, W = L >> C::kWordShift;
@@ -236,12 +256,19 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
                                         : C::left(wb, d > 0 ? pick(bmid, d - 1) : bhalo);
                 const uint32_t ha = odd ? C::left(wa, d > 0 ? pick(amid, d - 1) : ahalo)
                                         : C::right(d < 3 ? pick(amid, d + 1) : ahalo, wa);
+                C::counts(wa, np1, nm1, n0);
+                C::counts(wb, np1, nm1, n0);
+                if (MODEL == 0) {
+                    // every colour-0 cell carries 4 bonds: B = 4 N0 - 2 (misaligned pairs)
+                    nz += 32;
+                    diff += sd_add_ising4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
+                    sd_add_ising4(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
+                    continue;
+                }
                 C::pair(wa, pick(bup, d), nz, diff);
                 C::pair(wa, pick(bdn, d), nz, diff);
                 C::pair(wa, wb, nz, diff);
                 C::pair(wa, hb, nz, diff);
-                C::counts(wa, np1, nm1, n0);
-                C::counts(wb, np1, nm1, n0);
                 if (CB == 4) {
                     sd_add4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
                     sd_add4(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
@@ -736,17 +763,18 @@ hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s)
 // Persistent kernels use at most this many workgroups (a few per CU).
 constexpr uint32_t kMaxGrid = 2048;
 
-hipError_t launch_bmq(const Geom& g, int64_t* acc, hipStream_t s)
+hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s)
 {
     const int64_t rows = pick_rows(g.L, 16);
     const int64_t threads = g.Q * (g.L / rows);
     const uint32_t grid = (uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid);
-    if (g.cb == 1)
-        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
-                           (uint32_t)rows, acc);
+    const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
+    if (model == 2)
+        hipLaunchKernelGGL(bmq_kernel<2>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
+    else if (model == 1)
+        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
     else
-        hipLaunchKernelGGL(bmq_kernel<4>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), (uint32_t)g.L,
-                           (uint32_t)rows, acc);
+        hipLaunchKernelGGL(bmq_kernel<0>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
     return hipGetLastError();
 }
 
