@@ -330,50 +330,66 @@ __device__ __forceinline__ uint32_t nibble_bits(const uint4& v, bool invert)
     return r;
 }
 
-template <int MODEL, int RLO, int RHI, int C, int PAR>
-__device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int j, int (&ax)[33], int (&ay)[33])
+// Distances [RLO, RHI] along one axis (AXIS 0: x, 1: y) for the cells of
+// plane C in tile row lr (PAR: parity of y + C).
+template <int MODEL, int AXIS, int RLO, int RHI, int C, int PAR>
+__device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int j, int (&acc)[33])
 {
+    constexpr int Z = ShortTile<MODEL>::NB - 1;         // plane of nonzero bits (Blume-Capel)
     const uint32_t o = T.v[C][0][lr][j];
-    const uint32_t oz = MODEL == 1 ? T.v[C][1][lr][j] : 0u;
+    const uint32_t oz = MODEL == 1 ? T.v[C][Z][lr][j] : 0u;
     uint32_t w0[2], w1[2], z0[2], z1[2];
+    if (AXIS == 0) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        w0[p] = T.v[p][0][lr][j];
-        w1[p] = T.v[p][0][lr][j + 1];
-        z0[p] = MODEL == 1 ? T.v[p][ShortTile<MODEL>::NB - 1][lr][j] : 0u;
-        z1[p] = MODEL == 1 ? T.v[p][ShortTile<MODEL>::NB - 1][lr][j + 1] : 0u;
+        for (int p = 0; p < 2; ++p) {
+            w0[p] = T.v[p][0][lr][j];
+            w1[p] = T.v[p][0][lr][j + 1];
+            z0[p] = MODEL == 1 ? T.v[p][Z][lr][j] : 0u;
+            z1[p] = MODEL == 1 ? T.v[p][Z][lr][j + 1] : 0u;
+        }
     }
 #pragma unroll
     for (int r = RLO; r <= RHI; ++r) {
         const int pc = C ^ (r & 1);
-        const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);     // in-plane shift, 0..16
-        const uint32_t px = m ? funnel(w1[pc], w0[pc], m) : w0[pc];
-        const uint32_t py = T.v[pc][0][lr + r][j];
-        if (MODEL != 1) {
-            ax[r] += (int)popc(o ^ px);                 // pairs of opposite sign
-            ay[r] += (int)popc(o ^ py);
+        uint32_t pv, pz = 0;
+        if (AXIS == 0) {
+            const int m = (r & 1) ? ((r - 1) >> 1) + PAR : (r >> 1);     // in-plane shift, 0..16
+            pv = m ? funnel(w1[pc], w0[pc], m) : w0[pc];
+            if (MODEL == 1) pz = m ? funnel(z1[pc], z0[pc], m) : z0[pc];
         } else {
-            const uint32_t zx = (m ? funnel(z1[pc], z0[pc], m) : z0[pc]) & oz;
-            const uint32_t zy = T.v[pc][ShortTile<MODEL>::NB - 1][lr + r][j] & oz;
-            ax[r] += (int)popc(zx) - 2 * (int)popc(zx & (o ^ px));
-            ay[r] += (int)popc(zy) - 2 * (int)popc(zy & (o ^ py));
+            pv = T.v[pc][0][lr + r][j];
+            if (MODEL == 1) pz = T.v[pc][Z][lr + r][j];
+        }
+        if (MODEL != 1) {
+            acc[r] += (int)popc(o ^ pv);                // pairs of opposite sign
+        } else {
+            const uint32_t nz = pz & oz;
+            acc[r] += (int)popc(nz) - 2 * (int)popc(nz & (o ^ pv));
         }
     }
 }
 
-// Distances [RLO, RHI] over the thread's 4 rows of the current tile.
-template <int MODEL, int RLO, int RHI>
-__device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, int g, int (&ax)[33], int (&ay)[33])
+// Distances [RLO, RHI] along one axis over the thread's 8 rows of the tile.
+template <int MODEL, int AXIS, int RLO, int RHI>
+__device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, int g, int (&acc)[33])
 {
-    // tile rows 4g .. 4g + 3; the tile's first row is even, so the parity of
+    // tile rows 8g .. 8g + 7; the tile's first row is even, so the parity of
     // y + c is that of the local row + c
-    for (int k = 0; k < 4; k += 2) {
-        const int lr = 4 * g + k;
-        short_row<MODEL, RLO, RHI, 0, 0>(T, lr, j, ax, ay);
-        short_row<MODEL, RLO, RHI, 1, 1>(T, lr, j, ax, ay);
-        short_row<MODEL, RLO, RHI, 0, 1>(T, lr + 1, j, ax, ay);
-        short_row<MODEL, RLO, RHI, 1, 0>(T, lr + 1, j, ax, ay);
+    for (int k = 0; k < 8; k += 2) {
+        const int lr = 8 * g + k;
+        short_row<MODEL, AXIS, RLO, RHI, 0, 0>(T, lr, j, acc);
+        short_row<MODEL, AXIS, RLO, RHI, 1, 1>(T, lr, j, acc);
+        short_row<MODEL, AXIS, RLO, RHI, 0, 1>(T, lr + 1, j, acc);
+        short_row<MODEL, AXIS, RLO, RHI, 1, 0>(T, lr + 1, j, acc);
     }
+}
+
+template <int MODEL, int AXIS>
+__device__ __forceinline__ void short_tile(const ShortTile<MODEL>& T, int j, int g, int R, int (&acc)[33])
+{
+    short_chunk<MODEL, AXIS, 0, 10>(T, j, g, acc);
+    if (R > 10) short_chunk<MODEL, AXIS, 11, 21>(T, j, g, acc);
+    if (R > 21) short_chunk<MODEL, AXIS, 22, 32>(T, j, g, acc);
 }
 
 // Persistent over tiles: each workgroup loads tiles (strip of kSW words by
@@ -390,21 +406,50 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
     const uint32_t ntiles = nstrips * (L / kTH);
     const size_t plane_units = (size_t)L * Wp;      // 16-byte vectors (4-bit) or words (1-bit) per plane
     const uint4* P4 = reinterpret_cast<const uint4*>(planes);
+    // thread: word column j; waves 0 and 2 take the x axis, waves 1 and 3 the
+    // y axis (uniform per wave); the two 32-lane halves of a wave and the
+    // wave pair give the row group g, rows 8 g .. 8 g + 7 of the tile
     const int j = threadIdx.x & (kSW - 1);
-    const int g = threadIdx.x / kSW;
-    int ax[33], ay[33];
+    const int wave = threadIdx.x >> 6;
+    const int axis = wave & 1;
+    const int g = ((wave >> 1) << 1) | ((threadIdx.x >> 5) & 1);
+    int acc[33];
 #pragma unroll
-    for (int k = 0; k < 33; ++k) ax[k] = ay[k] = 0;
+    for (int k = 0; k < 33; ++k) acc[k] = 0;
     int64_t pairs = 0;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t q0 = (tile % nstrips) * kSW;
-        const uint32_t y0 = (tile / nstrips) * kTH;
+    // each workgroup takes a contiguous run of tiles, strip by strip and top
+    // to bottom within a strip, so a tile's 32 halo rows are the next tile's
+    // source rows: they move up in LDS and only 32 new rows are loaded
+    const uint32_t RT = L / kTH;                    // row tiles per strip
+    const uint32_t t_begin = (uint32_t)((uint64_t)blockIdx.x * ntiles / gridDim.x);
+    const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
+    constexpr uint32_t NB = ShortTile<MODEL>::NB;
+    constexpr uint32_t kRowElems = 2u * NB * (kSW + 1);   // elements of one tile row, both planes
+    for (uint32_t tile = t_begin; tile < t_end; ++tile) {
+        const uint32_t strip = tile / RT;
+        const uint32_t rt = tile - strip * RT;
+        const uint32_t q0 = strip * kSW;
+        const uint32_t y0 = rt * kTH;
+        const bool reuse = tile != t_begin && rt != 0;
         __syncthreads();
-        for (uint32_t idx = threadIdx.x; idx < 2u * kTileRows * (kSW + 1); idx += blockDim.x) {
-            const uint32_t c = idx / (kTileRows * (kSW + 1));
-            const uint32_t rem = idx - c * (kTileRows * (kSW + 1));
-            const uint32_t row = rem / (kSW + 1);
-            const uint32_t col = rem - row * (kSW + 1);
+        if (reuse) {
+            for (uint32_t idx = threadIdx.x; idx < kHalo * kRowElems; idx += blockDim.x) {
+                const uint32_t row = idx / kRowElems;
+                const uint32_t rem = idx - row * kRowElems;
+                const uint32_t c = rem / (NB * (kSW + 1));
+                const uint32_t rem2 = rem - c * (NB * (kSW + 1));
+                const uint32_t bp = rem2 / (kSW + 1);
+                const uint32_t col = rem2 - bp * (kSW + 1);
+                T.v[c][bp][row][col] = T.v[c][bp][row + kTH][col];
+            }
+            __syncthreads();
+        }
+        const uint32_t row0 = reuse ? (uint32_t)kHalo : 0u;
+        for (uint32_t idx = threadIdx.x; idx < 2u * (kTileRows - row0) * (kSW + 1); idx += blockDim.x) {
+            const uint32_t c = idx / ((kTileRows - row0) * (kSW + 1));
+            const uint32_t rem = idx - c * ((kTileRows - row0) * (kSW + 1));
+            const uint32_t row = row0 + rem / (kSW + 1);
+            const uint32_t col = rem % (kSW + 1);
             uint32_t y = y0 + row;
             while (y >= L) y -= L;
             uint32_t qq = q0 + col;
@@ -415,23 +460,22 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             } else {
                 const uint4 v = P4[at];
                 T.v[c][0][row][col] = nibble_bits<1>(v, false);            // n = 2: s = +1
-                if (MODEL == 1) T.v[c][ShortTile<MODEL>::NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+                if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
             }
         }
         __syncthreads();
         if (q0 + (uint32_t)j < Wp) {
-            short_chunk<MODEL, 0, 10>(T, j, g, ax, ay);
-            if (R > 10) short_chunk<MODEL, 11, 21>(T, j, g, ax, ay);
-            if (R > 21) short_chunk<MODEL, 22, 32>(T, j, g, ax, ay);
-            pairs += 256;          // 4 rows x 2 planes x 32 cells, per distance
+            if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, acc);
+            else short_tile<MODEL, 1>(T, j, g, R, acc);
+            pairs += 512;          // 8 rows x 2 planes x 32 cells, per distance
         }
     }
     int64_t v[66];
 #pragma unroll
     for (int k = 0; k < 33; ++k) {
-        const bool on = k <= R;
-        v[k] = !on ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)ax[k] : (int64_t)ax[k]);
-        v[33 + k] = !on ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)ay[k] : (int64_t)ay[k]);
+        const int64_t sk = k > R ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)acc[k] : (int64_t)acc[k]);
+        v[k] = axis == 0 ? sk : 0;
+        v[33 + k] = axis == 1 ? sk : 0;
     }
     block_add_xy<33>(v, Cx, Cy, red);
 }
