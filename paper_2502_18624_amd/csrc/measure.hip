@@ -20,6 +20,7 @@
 // unpacked to one int8 per site in LDS; along y the work runs over target
 // rows against a compact int8 copy of the sources, four products per dot4.
 #include <algorithm>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -562,110 +563,37 @@ __global__ __launch_bounds__(256) void zs_build_kernel(const uint32_t* __restric
                                                        int8_t* __restrict__ zs)
 {
     const uint32_t W = L >> Cell<CB>::kWordShift;
-    const uint32_t ns = L >> 4;                  // sources per row and source rows
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ns = L >> 4;                  // sources per row and source rows
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ns * ns) return;
-    const uint32_t b = g / ns, a = g - b * ns;
-    zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, 8 * a);
+    const uint64_t b = g / ns, a = g - b * ns;
+    zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, (uint32_t)(8 * a));
 }
 
-// Along x: one block per source row y = 16 b.  The row is unpacked into
-// one int8 per site (LDS, L bytes); thread t owns sources a = t, t + 256, ...
-constexpr int kXChunk = 16;
-
-// Cell of site (x, y) as a spin, read from the planes (used when a row of
-// int8 does not fit LDS).
+// Along x, one source row y = 16 b at a time (persistent over rows).  The
+// row is unpacked into LDS residue by residue, R_rho[a] = s(16 a + rho, y)
+// (P = L / 16 bytes each, L a power of two), so the partners of the sources
+// 16 a, a = 4 q .. 4 q + 3, at distance r are the bytes R_{r mod 16}[4 q +
+// (r >> 4) ...]: one v_alignbyte_b32 of two LDS words, and the four
+// products are one v_dot4.  LDS holds R_0 (the sources) and the residues
+// rho0 .. rho0 + G - 1; a launch handles the distances of those residues
+// (the host runs 16 / G passes when the whole row does not fit).  Wave w
+// owns the distances k = w, w + 16, ... and sweeps all sources of the row
+// for each, so it reduces once per distance and row.
 template <int CB>
-__device__ __forceinline__ int spin_at(const uint32_t* __restrict__ planes, size_t plane_words, uint32_t W, uint32_t x,
-                                       uint32_t y)
-{
-    const uint32_t c = (x + y) & 1u;
-    return Cell<CB>::spin(planes + c * plane_words + (size_t)y * W, x >> 1);
-}
-
-// Persistent over source rows.  With USE_LDS the row is unpacked into L
-// int8 spins ordered by residue mod 16 (spin x at (x & 15) * (L / 16) +
-// (x >> 4)), so the 64 lanes of a wave, holding consecutive sources a, read
-// consecutive bytes; per-distance sums gather in LDS and leave with one
-// atomic per distance per workgroup.  The row takes most of a CU's LDS, so
-// a workgroup is 1024 threads (16 waves) to hide LDS latency.
-template <int CB, bool USE_LDS>
 __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
-                                                      const int32_t* __restrict__ rlist, int nr,
-                                                      int64_t* __restrict__ Cx)
+                                                      const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
+                                                      uint32_t G, int64_t* __restrict__ Cx)
 {
-    extern __shared__ int sx_lds[];                 // nr int32 sums, then the row
+    extern __shared__ int sx_lds[];                 // nr int32 sums, R_0, then R_rho0 .. R_{rho0+G-1}
     int* sums = sx_lds;
-    int8_t* srow = reinterpret_cast<int8_t*>(sx_lds + nr);
-    const uint32_t W = L >> Cell<CB>::kWordShift;
-    const uint32_t NS = L >> 4;                     // sources per row
-    const uint32_t P = L >> 4;                      // spins per residue class
-    const size_t plane_words = (size_t)L * W;
-    for (int k = threadIdx.x; k < nr; k += blockDim.x) sums[k] = 0;
-    for (uint32_t b = blockIdx.x; b < (L >> 4); b += gridDim.x) {
-        const uint32_t y = 16 * b;
-        if (USE_LDS) {
-            __syncthreads();
-            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
-                const uint32_t c = idx >= W ? 1u : 0u;
-                const uint32_t wd = idx - c * W;
-                const uint32_t word = planes[c * plane_words + (size_t)y * W + wd];
-                const uint32_t par = (y + c) & 1u;              // x = 2 i + par
-#pragma unroll
-                for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
-                    const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
-                    const int sv = CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1 : (((word >> k) & 1u) ? 1 : -1);
-                    srow[(x & 15) * P + (x >> 4)] = (int8_t)sv;
-                }
-            }
-            __syncthreads();
-        }
-        for (int j0 = 0; j0 < nr; j0 += kXChunk) {
-            int acc[kXChunk];
-#pragma unroll
-            for (int k = 0; k < kXChunk; ++k) acc[k] = 0;
-            for (uint32_t a = threadIdx.x; a < NS; a += blockDim.x) {
-                const int src = USE_LDS ? (int)srow[a] : spin_at<CB>(planes, plane_words, W, 16 * a, y);
-#pragma unroll
-                for (int k = 0; k < kXChunk; ++k) {
-                    if (j0 + k < nr) {
-                        const uint32_t x = wrap(16 * a + (uint32_t)rlist[j0 + k], L);
-                        acc[k] += src * (USE_LDS ? (int)srow[(x & 15) * P + (x >> 4)]
-                                                 : spin_at<CB>(planes, plane_words, W, x, y));
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kXChunk; ++k) {
-                const int s2 = wave_sum_i32(acc[k]);
-                if ((threadIdx.x & 63) == 0 && j0 + k < nr) atomicAdd(&sums[j0 + k], s2);
-            }
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nr; k += blockDim.x)
-        if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
-}
-
-// Along x with the row in LDS (L a power of two, L bytes fit): the row is
-// stored residue by residue, R_rho[a] = s(16 a + rho, y) (P = L / 16 bytes
-// each), so the partners of the sources 16 a, a = 4 q .. 4 q + 3, at
-// distance r are the bytes R_{r mod 16}[4 q + (r >> 4) ...], one
-// v_alignbyte_b32 of two LDS words, and the four products are one v_dot4.
-// Wave w owns the distances k = w, w + 16, ... of the launch and sweeps all
-// sources of the row for each, so it reduces once per distance and row.
-template <int CB>
-__global__ __launch_bounds__(1024) void corr_sx_dot4_kernel(const uint32_t* __restrict__ planes, uint32_t L,
-                                                           const int32_t* __restrict__ rlist, int nr,
-                                                           int64_t* __restrict__ Cx)
-{
-    extern __shared__ int sx_lds[];                 // nr int32 sums, then the row
-    int* sums = sx_lds;
-    int8_t* srow = reinterpret_cast<int8_t*>(sx_lds + nr);
-    const uint32_t* srow_w = reinterpret_cast<const uint32_t*>(srow);
     const uint32_t W = L >> Cell<CB>::kWordShift;
     const uint32_t P = L >> 4;                      // bytes per residue class
     const uint32_t PQ = P >> 2;                     // words per residue class (a power of two)
+    int8_t* zrow = reinterpret_cast<int8_t*>(sx_lds + nr);
+    int8_t* grow = zrow + P;
+    const uint32_t* zrow_w = reinterpret_cast<const uint32_t*>(zrow);
+    const uint32_t* grow_w = reinterpret_cast<const uint32_t*>(grow);
     const size_t plane_words = (size_t)L * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
@@ -681,23 +609,27 @@ __global__ __launch_bounds__(1024) void corr_sx_dot4_kernel(const uint32_t* __re
 #pragma unroll
             for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
                 const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
-                const int sv = CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1 : (((word >> k) & 1u) ? 1 : -1);
-                srow[(x & 15) * P + (x >> 4)] = (int8_t)sv;
+                const int8_t sv = (int8_t)(CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1
+                                                   : (((word >> k) & 1u) ? 1 : -1));
+                const uint32_t rho = x & 15u, a = x >> 4;
+                if (rho == 0) zrow[a] = sv;
+                if (rho - rho0 < G) grow[(rho - rho0) * P + a] = sv;
             }
         }
         __syncthreads();
         for (int k = wave; k < nr; k += nwaves) {
             const uint32_t r = (uint32_t)rlist[k];
-            const uint32_t base = (r & 15u) * PQ;
+            if ((r & 15u) - rho0 >= G) continue;            // another pass's residue
+            const uint32_t base = ((r & 15u) - rho0) * PQ;
             const uint32_t sh = r >> 4;                     // whole sources of offset
             const uint32_t qs = sh >> 2, bs = sh & 3u;
             int acc = 0;
             for (uint32_t q = lane; q < PQ; q += 64) {
                 const uint32_t wi = (q + qs) & (PQ - 1);
-                const uint32_t lo = srow_w[base + wi];
-                const uint32_t hi = srow_w[base + ((wi + 1) & (PQ - 1))];
+                const uint32_t lo = grow_w[base + wi];
+                const uint32_t hi = grow_w[base + ((wi + 1) & (PQ - 1))];
                 const uint32_t part = __builtin_amdgcn_alignbyte(hi, lo, bs);
-                acc = __builtin_amdgcn_sdot4((int)srow_w[q], (int)part, acc, false);
+                acc = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)part, acc, false);
             }
             const int s2 = wave_sum_i32(acc);
             if (lane == 0) sums[k] += s2;
@@ -726,13 +658,18 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
 {
     const uint32_t W = L >> Cell<CB>::kWordShift;
     const uint32_t NS = L >> 4;                             // sources per row
-    uint32_t id = blockIdx.x;
+    // Workgroups go round-robin to the 8 XCDs.  The 16 residues of one
+    // (chunk, band, source chunk) read the same source rows for the dense
+    // distances, so they get ids 8 apart: consecutive on one XCD's L2.  The
+    // grid has 128 * ceil(N / 8) workgroups, N = nchunk * nband * nachunk.
+    const uint32_t jdx = blockIdx.x >> 3;
+    const uint32_t rho = jdx & 15u;
+    uint32_t id = ((jdx >> 4) << 3) | (blockIdx.x & 7u);
+    if (id >= nchunk * nband * nachunk) return;
     const uint32_t ac = id % nachunk;
     id /= nachunk;
     const uint32_t band = id % nband;
-    id /= nband;
-    const uint32_t chunk = id % nchunk;
-    const uint32_t rho = id / nchunk;
+    const uint32_t chunk = id / nband;
     const int p0 = res_off[rho] + (int)(chunk * kYChunk);
     const int p1 = res_off[rho + 1];
     if (p0 >= p1) return;
@@ -857,51 +794,61 @@ hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t*
 
 namespace {
 
+// LDS bytes the x-correlation kernel may use: 160 KiB, or less when the
+// environment variable MCL_SX_LDS_BUDGET says so (a test uses it to run the
+// multi-pass form at small L).
+size_t sx_lds_budget()
+{
+    size_t budget = 160u * 1024u;
+    if (const char* e = std::getenv("MCL_SX_LDS_BUDGET")) {
+        const long long v = std::atoll(e);
+        if (v > 0 && (size_t)v < budget) budget = (size_t)v;
+    }
+    return budget;
+}
+
 template <int CB>
 hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
     const uint32_t L = (uint32_t)g.L, nb = L / 16;
-    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((nb * nb + 255) / 256), dim3(256), 0, s, g.plane0, L, a.zs);
+    if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
+    const uint64_t nsrc = (uint64_t)nb * nb;
+    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((uint32_t)((nsrc + 255) / 256)), dim3(256), 0, s, g.plane0, L,
+                       a.zs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // along x: LDS holds the distance sums of a launch (<= 8192 distances
-    // each) and, when it fits in the 160 KiB of a workgroup, the int8 row
-    const int kMaxR = 8192;
+    // along x: LDS holds the distance sums of a launch, the source residue
+    // and a group of G residue rows (P = L / 16 bytes each)
+    const size_t P = nb, budget = sx_lds_budget();
     const uint32_t gx = std::min<uint32_t>(nb, 512);
-    for (int j0 = 0; j0 < a.nr; j0 += kMaxR) {
-        const int nr = std::min(kMaxR, a.nr - j0);
-        const size_t lds_sums = (size_t)nr * 4;
-        const bool use_lds = lds_sums + L <= 160u * 1024u;
-        const size_t lds = lds_sums + (use_lds ? L : 0);
-        // the dot4 form needs whole words per residue class and a power-of-two row
-        const bool dot4 = use_lds && (L & (L - 1)) == 0 && L >= 64;
-        static size_t attr_bytes[3] = {0, 0, 0};
-        const int fi = dot4 ? 2 : (use_lds ? 1 : 0);
-        const void* fn = dot4 ? (const void*)corr_sx_dot4_kernel<CB>
-                              : (use_lds ? (const void*)corr_sx_kernel<CB, true> : (const void*)corr_sx_kernel<CB, false>);
-        if (lds > 64u * 1024u && attr_bytes[fi] < lds) {
-            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    uint32_t G = 16;
+    while (G > 1 && 4u * 64u + P * (1 + G) > budget) G >>= 1;
+    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(P * (1 + G))) / 4));
+    if (P * (1 + G) + 4 > budget) return hipErrorInvalidValue;
+    static size_t attr_bytes = 0;
+    for (int j0 = 0; j0 < a.nr; j0 += max_r) {
+        const int nr = std::min(max_r, a.nr - j0);
+        const size_t lds = (size_t)nr * 4 + P * (1 + G);
+        if (lds > 64u * 1024u && attr_bytes < lds) {
+            e = hipFuncSetAttribute((const void*)corr_sx_kernel<CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
             if (e != hipSuccess) return e;
-            attr_bytes[fi] = lds;
+            attr_bytes = lds;
         }
-        if (dot4)
-            hipLaunchKernelGGL((corr_sx_dot4_kernel<CB>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
+        for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
+            hipLaunchKernelGGL((corr_sx_kernel<CB>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr, rho0, G,
                                a.Cx + j0);
-        else if (use_lds)
-            hipLaunchKernelGGL((corr_sx_kernel<CB, true>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
-                               a.Cx + j0);
-        else
-            hipLaunchKernelGGL((corr_sx_kernel<CB, false>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr,
-                               a.Cx + j0);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     const uint32_t nchunk = (uint32_t)((a.max_per_residue + kYChunk - 1) / kYChunk);
     const uint32_t nband = (nb + kYRows - 1) / kYRows;
     const uint32_t nachunk = (nb + 1023) / 1024;
     if (nchunk == 0) return hipSuccess;
-    hipLaunchKernelGGL(corr_sy_kernel<CB>, dim3(16u * nchunk * nband * nachunk), dim3(256), 0, s, g.plane0, L, a.zs,
-                       a.r, a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
+    const uint32_t nsy = nchunk * nband * nachunk;
+    hipLaunchKernelGGL(corr_sy_kernel<CB>, dim3(128u * ((nsy + 7) / 8)), dim3(256), 0, s, g.plane0, L, a.zs, a.r,
+                       a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
     return hipGetLastError();
 }
 

@@ -224,3 +224,21 @@ def test_group_sweep_equals_plain(mcl):
     for lat, (m, L, s, n, b, D) in zip(lats, specs):
         assert lat.t == n
         assert np.array_equal(lat.read(), _oracle_run(m, L, s, 0, n, b, D))
+
+
+@pytest.mark.parametrize("budget,model", [(2048, 0), (768, 1), (2048, 2), (768, 2)])
+def test_sampled_x_correlation_in_residue_passes(mcl, monkeypatch, budget, model):
+    """The x-correlation of the sampled sources keeps the source residue and a
+    group of residue rows in LDS; lattices whose rows do not fit (L >= 2^18)
+    take several passes.  Forcing a small LDS budget runs that form at
+    L = 4096 (budget 2048: 4 residues per pass; 768: one, with the distance
+    list split over several launches) against the oracle."""
+    print("sampled x in passes", budget, model, flush=True)
+    monkeypatch.setenv("MCL_SX_LDS_BUDGET", str(budget))
+    L = 4096
+    lat = mcl.Lattice(model, L, 31 + model)
+    lat.sweep(3, BETA_C, 1.0)
+    s = lat.read()
+    m = lat.measure(mcl.CORR_PROTOCOL)
+    Cx, Cy, ns = oracle.corr(s, oracle.CORR_PROTOCOL, m["r"])
+    assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy)
