@@ -182,9 +182,12 @@ int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, i
  * (each workgroup belongs to one replica, so its parameters are
  * wave-uniform).  All lattices must use the stream of hs[0] (MCL_EARG
  * otherwise).  Every lattice ends bit-identical to n[i] sweep() calls on it
- * alone, whatever the tuning.  The library keeps a few small workspaces of
- * its own (descriptors, pinned staging, captured graphs), allocated on first
- * use and grown when a larger group arrives; they are never freed. */
+ * alone, whatever the tuning.  1-bit lattices (MCL_ISING_LUT) advance
+ * through sweep() within the call.  MCL_ERANGE if the replicas of one model
+ * need more than 2^24 workgroups (2^32 work-items) in one launch.  The
+ * library keeps a few small workspaces of its own (descriptors, pinned
+ * staging, captured graphs), allocated on first use and grown when a larger
+ * group arrives; they are never freed. */
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n,
                 const double* beta, const double* D);
 

@@ -356,6 +356,8 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
             }
             const int64_t threads = h->g.Q * (h->L / d.rows);
             d.wg_begin = wgs[m];
+            // one launch covers at most 2^32 work-items (2^24 workgroups)
+            if ((int64_t)wgs[m] + (threads + 255) / 256 > (int64_t(1) << 24)) return MCL_ERANGE;
             wgs[m] += (uint32_t)((threads + 255) / 256);
             hd[k++] = d;
         }

@@ -564,10 +564,11 @@ __global__ __launch_bounds__(256) void zs_build_kernel(const uint32_t* __restric
 {
     const uint32_t W = L >> Cell<CB>::kWordShift;
     const uint64_t ns = L >> 4;                  // sources per row and source rows
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ns * ns) return;
-    const uint64_t b = g / ns, a = g - b * ns;
-    zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, (uint32_t)(8 * a));
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ns * ns;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = g / ns, a = g - b * ns;
+        zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, (uint32_t)(8 * a));
+    }
 }
 
 // Along x, one source row y = 16 b at a time (persistent over rows).  The
@@ -813,8 +814,9 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     const uint32_t L = (uint32_t)g.L, nb = L / 16;
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
     const uint64_t nsrc = (uint64_t)nb * nb;
-    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((uint32_t)((nsrc + 255) / 256)), dim3(256), 0, s, g.plane0, L,
-                       a.zs);
+    // a grid of at most 2^20 workgroups strides over the (L / 16)^2 sources
+    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((uint32_t)std::min<uint64_t>((nsrc + 255) / 256, 1u << 20)),
+                       dim3(256), 0, s, g.plane0, L, a.zs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // along x: LDS holds the distance sums of a launch, the source residue

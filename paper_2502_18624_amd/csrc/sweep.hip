@@ -1,5 +1,7 @@
 // Initial state and the one-lattice half-sweep kernel for gfx950 (rows a1,
 // a3, a4); the per-thread update is in sweep_device.h.
+#include <algorithm>
+
 #include "internal.h"
 #include "sweep_device.h"
 
@@ -10,12 +12,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // a1: initial state.  One thread per 32-bit word (8 cells) of one plane.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes, int64_t L, int64_t W,
-                                                   int model, int init_state, uint32_t k0, uint32_t k1)
+// Word g of the two planes (plane-major, then row, then word).
+__device__ __forceinline__ uint32_t init_word(int64_t g, int64_t L, int64_t W, int model, int init_state,
+                                              uint32_t k0, uint32_t k1)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = 2 * L * W;
-    if (g >= total) return;
     const int color = (int)(g / (L * W));
     const int64_t rem = g - (int64_t)color * L * W;
     const int64_t y = rem / W;
@@ -45,7 +45,16 @@ __global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes
         }
         word |= (uint32_t)(s + 1) << (4 * j);
     }
-    planes[g] = word;
+    return word;
+}
+
+__global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes, int64_t L, int64_t W,
+                                                   int model, int init_state, uint32_t k0, uint32_t k1)
+{
+    const int64_t total = 2 * L * W;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x)
+        planes[g] = init_word(g, L, W, model, init_state, k0, k1);
 }
 
 template <int MODEL, bool HI0, int COLOR>
@@ -65,31 +74,31 @@ __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ 
 }
 
 // a1 for the 1-bit layout: one thread per word (32 cells) of one plane.
-__global__ __launch_bounds__(256) void init1_kernel(uint32_t* __restrict__ planes, int64_t L, int64_t W,
-                                                    int init_state, uint32_t k0, uint32_t k1)
+__device__ __forceinline__ uint32_t init1_word(int64_t g, int64_t L, int64_t W, int init_state, uint32_t k0,
+                                               uint32_t k1)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 2 * L * W) return;
     const int color = (int)(g / (L * W));
     const int64_t rem = g - (int64_t)color * L * W;
     const int64_t y = rem / W;
     const int64_t wd = rem - y * W;
+    if (init_state == 1) return 0xFFFFFFFFu;
+    if (init_state == 2) return 0u;
     uint32_t word = 0;
     for (int j = 0; j < 32; ++j) {
-        uint32_t bit;
-        if (init_state == 1) {
-            bit = 1;
-        } else if (init_state == 2) {
-            bit = 0;
-        } else {
-            const int64_t x = 2 * (wd * 32 + j) + ((y + color) & 1);
-            const uint64_t n = (uint64_t)(y * L + x);
-            const Philox4 o = philox4x32_10(dev::lo32(n >> 2), dev::hi32(n >> 2), 0u, 4u, k0, k1);
-            bit = philox_word(o, (int)(n & 3)) < 0x80000000u ? 1u : 0u;
-        }
-        word |= bit << j;
+        const int64_t x = 2 * (wd * 32 + j) + ((y + color) & 1);
+        const uint64_t n = (uint64_t)(y * L + x);
+        const Philox4 o = philox4x32_10(dev::lo32(n >> 2), dev::hi32(n >> 2), 0u, 4u, k0, k1);
+        word |= (philox_word(o, (int)(n & 3)) < 0x80000000u ? 1u : 0u) << j;
     }
-    planes[g] = word;
+    return word;
+}
+
+__global__ __launch_bounds__(256) void init1_kernel(uint32_t* __restrict__ planes, int64_t L, int64_t W,
+                                                    int init_state, uint32_t k0, uint32_t k1)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < 2 * L * W;
+         g += (int64_t)gridDim.x * blockDim.x)
+        planes[g] = init1_word(g, L, W, init_state, k0, k1);
 }
 
 // Bucket table of the 1-bit mode (one thread per bucket): for the draws u
@@ -154,10 +163,14 @@ int64_t band_rows(int64_t L)
 
 }  // namespace
 
+// One launch covers at most 2^32 work-items per dimension: the init
+// kernels stride over the planes with a grid of at most 2^20 workgroups.
+constexpr int64_t kMaxInitBlocks = int64_t(1) << 20;
+
 hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, hipStream_t s)
 {
     const int64_t total = 2 * g.L * g.W;
-    const int64_t blocks = (total + 255) / 256;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, kMaxInitBlocks);
     hipLaunchKernelGGL(init_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, g.plane0, g.L, g.W, model,
                        init_state, (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();
@@ -202,7 +215,8 @@ static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t
 hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_t s)
 {
     const int64_t total = 2 * g.L * g.W;
-    hipLaunchKernelGGL(init1_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, g.plane0, g.L, g.W,
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, kMaxInitBlocks);
+    hipLaunchKernelGGL(init1_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, g.plane0, g.L, g.W,
                        init_state, (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();
 }
