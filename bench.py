@@ -207,6 +207,62 @@ def run_ising_1bit(args):
     return res
 
 
+# Single-GPU throughput against L (the paper's Tables 1 and 2; GB200
+# figures, context only).
+PAPER_TABLE_ISING_1BIT = {13: 1051, 14: 1530, 15: 1741, 16: 1784, 17: 1797, 18: 1801, 19: 1802, 20: 1802}
+PAPER_TABLE_BC = {12: 304, 13: 633, 14: 839, 15: 922, 16: 941, 17: 947, 18: 949, 19: 948}
+
+
+def run_scan(args):
+    """Sweep-only updates/ns against L for the three models: random start,
+    T = T_c (Blume-Capel T = 1.4, D = 1), about 2e12 updates per size, HIP
+    events around the sweep calls; sizes that do not fit the free device
+    memory are skipped."""
+    import gc
+
+    import torch
+
+    import paper_2502_18624_amd as mcl
+    stream = torch.cuda.current_stream()
+    gc.collect()
+    torch.cuda.empty_cache()                             # earlier legs' cached blocks
+    legs = [(mcl.ISING_LUT, range(13, 21), BETA_C, 0.0, PAPER_TABLE_ISING_1BIT),
+            (mcl.BC, range(12, 20), 1 / 1.4, 1.0, PAPER_TABLE_BC),
+            (mcl.ISING, range(12, 20), BETA_C, 0.0, {})]
+    names = {mcl.ISING_LUT: "ising_1bit", mcl.BC: "blume_capel", mcl.ISING: "ising_4bit"}
+    out = {}
+    for model, ks, beta, D, paper in legs:
+        rows = []
+        for k in ks:
+            L = 2 ** k
+            free, _ = torch.cuda.mem_get_info()
+            if mcl.query_bytes(model, L) + (1 << 30) > free:
+                rows.append({"log2L": k, "skipped": "does not fit the free device memory"})
+                continue
+            n = max(2, int(round(args.scan_updates / float(L * L))))
+            lat = mcl.Lattice(model, L, 7 + k, stream=stream)
+            lat.sweep(2, beta, D)                        # warm-up
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.sweep(n, beta, D)
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            rec = {"log2L": k, "sweeps": n, "updates_per_ns": round(float(L) * L * n / (ms * 1e6), 1)}
+            if k in paper:
+                rec["paper_gb200"] = paper[k]
+            rows.append(rec)
+            log("  scan %s L=2^%d: %.1f updates/ns" % (names[model], k, rec["updates_per_ns"]))
+            lat.free()
+            del lat
+            gc.collect()
+            torch.cuda.empty_cache()
+        out[names[model]] = rows
+    out["workload"] = ("one lattice per size, random start, T = T_c (Blume-Capel T = 1.4, D = 1), about %.0e "
+                       "updates per size, sweep-only (HIP events)" % args.scan_updates)
+    return out
+
+
 def run_batched(args):
     """Batched vs plain on the same replica set: group_sweep (autotuned) and
     one lattice per launch, sweep by sweep."""
@@ -373,8 +429,9 @@ def main():
     ap.add_argument("--L", type=int, default=2 ** 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
-    ap.add_argument("--extras", default="bc,lut,batched,serving",
-                    help="comma list of the further legs: bc, lut, batched, serving")
+    ap.add_argument("--extras", default="bc,lut,batched,serving,scan",
+                    help="comma list of the further legs: bc, lut, batched, serving, scan")
+    ap.add_argument("--scan-updates", type=float, default=2e12, help="updates per size in the scan leg")
     ap.add_argument("--bc-sweeps", type=int, default=2000)
     ap.add_argument("--lut-sweeps", type=int, default=2000)
     ap.add_argument("--replicas", type=int, default=512)
@@ -400,6 +457,9 @@ def main():
     if "serving" in extras:
         log("bench: serving")
         res["serving"] = run_serving(args)
+    if "scan" in extras:
+        log("bench: throughput against L")
+        res["scan"] = run_scan(args)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         res["cpu_baseline"] = cpu_baseline()

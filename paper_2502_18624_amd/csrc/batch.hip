@@ -45,10 +45,15 @@ __global__ __launch_bounds__(256) void group_half_kernel(const GroupDesc* __rest
     const uint32_t T4 = __builtin_amdgcn_readfirstlane(d.T4);
     const uint32_t T8 = __builtin_amdgcn_readfirstlane(d.T8);
     const uint32_t t = d.t0 + s;
-    if (d.hi0)
-        dev::band_update<MODEL, true, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, T4, T8, s_tab.e);
+    uint32_t hu;
+    const int hm = dev::counter_mode(d.hi0 != 0, ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2,
+                                     ((uint64_t)(y0 + d.rows - 1) * (L >> 1) + 32u * q + 31u) >> 2, hu);
+    if (hm == 0)
+        dev::band_update<MODEL, 0, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, s_tab.e);
+    else if (hm == 1)
+        dev::band_update<MODEL, 1, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, hu, T4, T8, s_tab.e);
     else
-        dev::band_update<MODEL, false, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, T4, T8, s_tab.e);
+        dev::band_update<MODEL, 2, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, s_tab.e);
 }
 
 }  // namespace

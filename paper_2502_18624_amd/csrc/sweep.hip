@@ -70,7 +70,16 @@ __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ 
     const uint32_t band = g / Q;
     const uint32_t y0 = band * rows;
     if (y0 >= L) return;
-    dev::band_update<MODEL, HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, T4, T8, s_tab.e);
+    // blocks of the band: accept draws of in-colour cells y0 L/2 + 32 q .. (y0 + rows - 1) L/2 + 32 q + 31
+    uint32_t hu;
+    const int hm = dev::counter_mode(HI0, ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2,
+                                     ((uint64_t)(y0 + rows - 1) * (L >> 1) + 32u * q + 31u) >> 2, hu);
+    if (hm == 0)
+        dev::band_update<MODEL, 0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, 0u, T4, T8, s_tab.e);
+    else if (hm == 1)
+        dev::band_update<MODEL, 1, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, hu, T4, T8, s_tab.e);
+    else
+        dev::band_update<MODEL, 2, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, 0u, T4, T8, s_tab.e);
 }
 
 // a1 for the 1-bit layout: one thread per word (32 cells) of one plane.
@@ -150,15 +159,27 @@ __global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ ow
     const uint32_t q = g % Q;
     const uint32_t y0 = (g / Q) * rows;
     if (y0 >= L) return;
-    dev::band_update_lut<HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, s_b, s_lut, tab.T[8], tab.kmax);
+    // blocks of the band: groups of 16 in-colour cells, y0 L/2 + 128 q .. (y0 + rows - 1) L/2 + 128 q + 127
+    uint32_t hu;
+    const int hm = dev::counter_mode(HI0, ((uint64_t)y0 * (L >> 1) + 128u * q) >> 4,
+                                     ((uint64_t)(y0 + rows - 1) * (L >> 1) + 128u * q + 127u) >> 4, hu);
+    if (hm == 0)
+        dev::band_update_lut<0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, 0u, s_b, s_lut, tab.T[8], tab.kmax);
+    else if (hm == 1)
+        dev::band_update_lut<1, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, hu, s_b, s_lut, tab.T[8], tab.kmax);
+    else
+        dev::band_update_lut<2, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, 0u, s_b, s_lut, tab.T[8], tab.kmax);
 }
 
-int64_t band_rows(int64_t L)
+// Band height (rows per thread, even, dividing L): 32 amortises the two
+// halo rows of the other plane (1/16 extra reads); smaller lattices take
+// shorter bands so that a launch still has about 2048 waves (8 per CU) --
+// Q vectors per row, L rows.
+int64_t band_rows(int64_t Q, int64_t L)
 {
-    // even; deep enough to amortise the two halo rows (1/16 extra reads of
-    // the other plane at 32 rows), shallow enough for many thousand waves.
-    // L is a multiple of 64, so both choices divide it.
-    return L >= 4096 ? 32 : 16;
+    int64_t rows = 32;
+    while (rows > 2 && Q * (L / rows) < 131072) rows >>= 1;
+    return rows;
 }
 
 }  // namespace
@@ -190,7 +211,7 @@ static void launch_model(dim3 grid, hipStream_t s, uint32_t* own, const uint32_t
 
 static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s, int model)
 {
-    const int64_t rows = band_rows(g.L);
+    const int64_t rows = band_rows(g.Q, g.L);
     const int64_t threads = g.Q * (g.L / rows);
     const int64_t blocks = (threads + 255) / 256;
     BCTable tbl{};
@@ -232,7 +253,7 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, 
                            const void* buckets, hipStream_t s)
 {
     const uint2* bk = reinterpret_cast<const uint2*>(buckets);
-    const int64_t rows = g.L >= 4096 ? 32 : 16;
+    const int64_t rows = band_rows(g.Q, g.L);
     const int64_t threads = g.Q * (g.L / rows);
     const dim3 grid((uint32_t)((threads + 255) / 256));
     uint32_t* own = g.plane(color);

@@ -22,6 +22,16 @@ namespace dev {
 __device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
 __device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
 
+// High word of a Philox counter: 0 while every block index of the lattice
+// fits 32 bits (HM 0); the wave-uniform value hu when the caller has shown
+// that all of the wave's blocks share it (HM 1, kept in a scalar register);
+// else per lane (HM 2).
+template <int HM>
+__device__ __forceinline__ uint32_t hiw(uint64_t b, uint32_t hu)
+{
+    return HM == 0 ? 0u : (HM == 1 ? hu : hi32(b));
+}
+
 __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 {
     return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
@@ -36,9 +46,9 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 // (acc = acc + acc + carry) and lets word d read its cells' bits at nibble
 // bit 0 as (mask >> d) & 0x11111111.
 // ---------------------------------------------------------------------------
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t color, uint32_t k0, uint32_t k1,
-                                             uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
+                                             uint32_t hu, uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
 {
     uint32_t a4 = 0, a8 = 0;
 #pragma unroll
@@ -47,7 +57,7 @@ __device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
+            P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
         }
 #pragma unroll
         for (int jj = 3; jj >= 0; --jj)
@@ -80,13 +90,13 @@ __device__ __forceinline__ uint32_t horizontal(const uint4& mid, int d, uint32_t
 // with three, e^{-8 beta} with four) is: flip iff m + [u < T4] + [u < T8]
 // >= 2, since T8 <= T4.  Adding 6 moves that test to nibble bit 3.
 // ---------------------------------------------------------------------------
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
                                            uint32_t halo, bool odd, uint64_t blk0, uint32_t t, uint32_t color,
-                                           uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8)
+                                           uint32_t k0, uint32_t k1, uint32_t hu, uint32_t T4, uint32_t T8)
 {
     uint32_t m4, m8;
-    accept_masks<HI0>(blk0, t, color, k0, k1, T4, T8, m4, m8);
+    accept_masks<HM>(blk0, t, color, k0, k1, hu, T4, T8, m4, m8);
     uint32_t res[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -162,10 +172,11 @@ __device__ __forceinline__ void load_bc_table(BCLds& lds, const uint2* __restric
     __syncthreads();
 }
 
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
                                         uint32_t halo, bool odd, uint64_t blk0, uint32_t pbits, uint32_t t,
-                                        uint32_t color, uint32_t k0, uint32_t k1, const uint2* __restrict__ tab)
+                                        uint32_t color, uint32_t k0, uint32_t k1, uint32_t hu,
+                                        const uint2* __restrict__ tab)
 {
     uint32_t ev[4], od[4], nxt[4];
 #pragma unroll
@@ -188,7 +199,7 @@ __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, color, k0, k1);
+            P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
         }
 #pragma unroll
         for (int jj = 3; jj >= 0; --jj)
@@ -228,10 +239,10 @@ struct RowState {
     uint4 up, mid;
 };
 
-template <int MODEL, bool HI0, bool ODD>
+template <int MODEL, int HM, bool ODD>
 __device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__ oth_col0, uint32_t y, uint32_t L,
                                          uint32_t Q, uint32_t W, uint32_t hwl, uint32_t hwr, uint32_t color,
-                                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8,
+                                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t hu, uint32_t T4, uint32_t T8,
                                          const uint2* tab)
 {
     const uint4* pdn = (y + 1 == L) ? oth_col0 : st.pcur + Q;
@@ -240,12 +251,12 @@ __device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__
     const uint32_t halo = st.hrow[ODD ? hwr : hwl];
     uint4 res;
     if (MODEL == 0) {
-        res = ising_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, t, color, k0, k1, T4, T8);
+        res = ising_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, t, color, k0, k1, hu, T4, T8);
     } else {
         const uint64_t pb = st.kv >> 7;
-        const Philox4 p = philox4x32_10(lo32(pb), HI0 ? 0u : hi32(pb), t, 2u + color, k0, k1);
+        const Philox4 p = philox4x32_10(lo32(pb), HM == 0 ? 0u : hi32(pb), t, 2u + color, k0, k1);
         const uint32_t pbits = philox_word(p, (int)((st.kv >> 5) & 3));
-        res = bc_vec<HI0>(src, st.up, dn, st.mid, halo, ODD, st.blk, pbits, t, color, k0, k1, tab);
+        res = bc_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, pbits, t, color, k0, k1, hu, tab);
     }
     *st.pown = res;
     st.up = st.mid;
@@ -259,10 +270,10 @@ __device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__
 
 // One thread's share of a half-sweep: column vector q of rows
 // [y0, y0 + rows) of an L x L lattice (rows even, y0 even).
-template <int MODEL, bool HI0, int COLOR>
+template <int MODEL, int HM, int COLOR>
 __device__ __forceinline__ void band_update(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth, uint32_t L,
                                             uint32_t rows, uint32_t q, uint32_t y0, uint32_t t, uint32_t k0,
-                                            uint32_t k1, uint32_t T4, uint32_t T8, const uint2* tab)
+                                            uint32_t k1, uint32_t hu, uint32_t T4, uint32_t T8, const uint2* tab)
 {
     const uint32_t Q = L >> 6;
     const uint32_t W = L >> 4;
@@ -279,8 +290,8 @@ __device__ __forceinline__ void band_update(uint32_t* __restrict__ own, const ui
     const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;     // word right of the vector
     for (uint32_t r = 0; r < rows; r += 2) {
         // even row y: parity of y + c is c; odd row: 1 - c
-        row_step<MODEL, HI0, COLOR == 1>(st, oth4, y0 + r, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8, tab);
-        row_step<MODEL, HI0, COLOR == 0>(st, oth4, y0 + r + 1, L, Q, W, hwl, hwr, COLOR, t, k0, k1, T4, T8, tab);
+        row_step<MODEL, HM, COLOR == 1>(st, oth4, y0 + r, L, Q, W, hwl, hwr, COLOR, t, k0, k1, hu, T4, T8, tab);
+        row_step<MODEL, HM, COLOR == 0>(st, oth4, y0 + r + 1, L, Q, W, hwl, hwr, COLOR, t, k0, k1, hu, T4, T8, tab);
     }
 }
 
@@ -309,15 +320,15 @@ __device__ __forceinline__ uint32_t lut_lookup(const uint32_t* __restrict__ T, u
 
 // Random bits of the 32 cells whose 8 groups of 4 start at group g0 (a
 // multiple of 8): Philox blocks g0/4 and g0/4 + 1 of `stream`.
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
-                                             const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
+                                             uint32_t hu, const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
 {
     uint32_t w = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint64_t b = (g0 >> 2) + h;
-        const Philox4 P = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, stream, k0, k1);
+        const Philox4 P = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, stream, k0, k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) w |= lut_lookup(T, T8, kmax, philox_word(P, j)) << (4 * (4 * h + j));
     }
@@ -331,16 +342,16 @@ __device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t s
 // with any such draw takes the exact search instead.
 constexpr int kLutBuckets = 4096;
 
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
-                                                  const uint2* __restrict__ B, const uint32_t* __restrict__ T,
-                                                  uint32_t T8, uint32_t kmax)
+                                                  uint32_t hu, const uint2* __restrict__ B,
+                                                  const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
 {
     uint32_t w = 0, flags = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint64_t b = (g0 >> 2) + h;
-        const Philox4 P = philox4x32_10(lo32(b), HI0 ? 0u : hi32(b), t, stream, k0, k1);
+        const Philox4 P = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, stream, k0, k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t u = philox_word(P, j);
@@ -350,14 +361,14 @@ __device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint3
             w |= k << (4 * (4 * h + j));
         }
     }
-    if (flags >> 31) w = lut_word<HI0>(g0, t, stream, k0, k1, T, T8, kmax);
+    if (flags >> 31) w = lut_word<HM>(g0, t, stream, k0, k1, hu, T, T8, kmax);
     return w;
 }
 
-template <bool HI0>
+template <int HM>
 __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
                                          uint32_t halo, bool odd, uint64_t kv, uint32_t t, uint32_t color,
-                                         uint32_t k0, uint32_t k1, const uint2* __restrict__ B,
+                                         uint32_t k0, uint32_t k1, uint32_t hu, const uint2* __restrict__ B,
                                          const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
 {
     uint32_t res[4];
@@ -372,8 +383,8 @@ __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, cons
         const uint32_t eq4 = ~(b0 | b1 | b2 | b3);
         const uint32_t eq3 = (t1 ^ t2) & ~(u1 | u2);
         const uint64_t g0 = (kv + 32u * d) >> 2;
-        const uint32_t e4 = lut_word_fast<HI0>(g0, t, 8u + 2u * color, k0, k1, B, T, T8, kmax);
-        const uint32_t e8 = lut_word_fast<HI0>(g0, t, 9u + 2u * color, k0, k1, B, T, T8, kmax) & e4;
+        const uint32_t e4 = lut_word_fast<HM>(g0, t, 8u + 2u * color, k0, k1, hu, B, T, T8, kmax);
+        const uint32_t e8 = lut_word_fast<HM>(g0, t, 9u + 2u * color, k0, k1, hu, B, T, T8, kmax) & e4;
         // a spin keeps its value only when four neighbours agree and its
         // e^{-8 beta} bit is clear, or three agree and its e^{-4 beta} bit is clear
         const uint32_t keep = (eq4 & ~e8) | (eq3 & ~e4);
@@ -384,11 +395,11 @@ __device__ __forceinline__ uint4 lut_vec(const uint4& src, const uint4& up, cons
 
 // One thread's share of a 1-bit half-sweep: column vector q (128 cells) of
 // rows [y0, y0 + rows) (rows even, y0 even).
-template <bool HI0, int COLOR>
+template <int HM, int COLOR>
 __device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
                                                 uint32_t L, uint32_t rows, uint32_t q, uint32_t y0, uint32_t t,
-                                                uint32_t k0, uint32_t k1, const uint2* B, const uint32_t* T,
-                                                uint32_t T8, uint32_t kmax)
+                                                uint32_t k0, uint32_t k1, uint32_t hu, const uint2* B,
+                                                const uint32_t* T, uint32_t T8, uint32_t kmax)
 {
     const uint32_t Q = L >> 8;                  // 16-byte vectors per row
     const uint32_t W = L >> 6;                  // words per row
@@ -407,7 +418,7 @@ __device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, cons
         const uint4 dn = *((y + 1 == L) ? oth4 : pcur + Q);
         const uint4 src = *pown;
         const uint32_t halo = hrow[odd ? hwr : hwl];
-        *pown = lut_vec<HI0>(src, up, dn, mid, halo, odd, kv, t, COLOR, k0, k1, B, T, T8, kmax);
+        *pown = lut_vec<HM>(src, up, dn, mid, halo, odd, kv, t, COLOR, k0, k1, hu, B, T, T8, kmax);
         up = mid;
         mid = dn;
         pcur += Q;
@@ -415,6 +426,19 @@ __device__ __forceinline__ void band_update_lut(uint32_t* __restrict__ own, cons
         hrow += W;
         kv += L >> 1;
     }
+}
+
+// The counter mode of a thread's band whose Philox blocks run from b_first
+// to b_last: 0 while every block index of the lattice fits 32 bits (hi0),
+// else 1 with hu the high word when the whole wave shares it (for L a
+// power of two it changes only between bands), else 2 (per lane).
+__device__ __forceinline__ int counter_mode(bool hi0, uint64_t b_first, uint64_t b_last, uint32_t& hu)
+{
+    hu = 0;
+    if (hi0) return 0;
+    const uint32_t hf = hi32(b_first);
+    hu = __builtin_amdgcn_readfirstlane(hf);
+    return __all(hf == hu && hi32(b_last) == hu) ? 1 : 2;
 }
 
 }  // namespace dev

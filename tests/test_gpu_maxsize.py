@@ -76,3 +76,28 @@ def test_largest_lattice(mcl, model, L, seed):
     up.free()
     del lat, up, mem
     _release()
+
+
+@pytest.mark.parametrize("model,L,shift", [(0, 185408, 2), (1, 185408, 2), (2, 370944, 4)])
+def test_counter_high_word_changes_inside_a_band(mcl, model, L, shift):
+    """L not a power of two, just large enough that the Philox block index
+    k >> shift of the in-colour index k passes 2^32 inside the lattice, in
+    the middle of a band of rows: the waves there take the per-lane form of
+    the counter.  Windows around the crossing against the oracle."""
+    print("high word inside a band", model, L, flush=True)
+    n, seed, beta, D = 2, 1007, BETA_C if model != 1 else 1 / 1.4, 1.0
+    k = 1 << (32 + shift)                           # first in-colour index of block 2^32
+    yb, ib = divmod(k, L // 2)
+    assert 0 < yb < L - 1
+    lat = mcl.Lattice(model, L, seed)
+    lat.sweep(n, beta, D)
+    W, pad = 32, 2 * n
+    P = W + 2 * pad
+    for dx in (-40, 0, 24):
+        x0, y0 = (2 * ib + dx) % L, yb - W // 2
+        got = lat.read_window(x0, y0, W, W)
+        patch = oracle.window_run(model, L, seed, (x0 - pad) % L, (y0 - pad) % L, P, n, beta, D)
+        assert np.array_equal(got, patch[pad:pad + W, pad:pad + W]), (x0, y0)
+    lat.free()
+    del lat
+    _release()
