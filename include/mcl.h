@@ -113,14 +113,14 @@ typedef struct mcl_measure_out {
  * plus measurement scratch. */
 int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes);
 
-/* a1 -- Create a handle and write the initial state (section 1: quench
+/* Create a handle and write the initial state (section 1: quench
  * from a high temperature; see MCL_INIT_*).  dev_mem: caller-owned device
  * buffer of dev_bytes >= mcl_query_bytes(); hip_stream: stream for all of
  * this handle's work.  The sweep counter t starts at 0. */
 int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int init_state,
                  void* dev_mem, int64_t dev_bytes, void* hip_stream);
 
-/* a2..a5 -- n checkerboard sweeps (section 3.1: colour 0, then colour 1)
+/* n checkerboard sweeps (section 3.1: colour 0, then colour 1)
  * of single-spin Metropolis updates (section 1) at inverse temperature beta
  * and crystal field D (ignored for Ising).  Ising: a spin with 3 aligned
  * neighbours flips with probability e^{-4 beta}, with 4 with e^{-8 beta},
@@ -130,7 +130,7 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
  * Asynchronous on the handle's stream; advances t by n. */
 int sweep(mcl_lattice* h, int64_t n, double beta, double D);
 
-/* a6..a8 -- B, M, Q, spin counts and, if corr_mode != NONE, the
+/* B, M, Q, spin counts and, if corr_mode != NONE, the
  * correlation sums along both axes at the distances of the mode for the
  * current t (section 3.3).  Synchronous.  MCL_EBUFSZ if r_cap < needed
  * (out->n_r then holds the needed size). */
@@ -176,7 +176,7 @@ int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t);
 /* Handle state. */
 int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, int64_t* t);
 
-/* a9 -- Batched path: advance `count` independent lattices (any mix of
+/* Batched path: advance `count` independent lattices (any mix of
  * models, sizes, beta and D) by n[i] sweeps each.  Replicas advance sweep by
  * sweep together: one launch per model and colour covers every replica
  * (each workgroup belongs to one replica, so its parameters are

@@ -85,8 +85,7 @@ def lib():
     if _lib_handle is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
-                "libmcl.so is not built (%s); run __graft_entry__.build() or "
-                "python paper_2502_18624_amd/build.py" % LIB_PATH)
+                "libmcl.so is not built (%s); run python paper_2502_18624_amd/build.py" % LIB_PATH)
         h = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(h, name)

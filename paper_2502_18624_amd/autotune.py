@@ -1,4 +1,4 @@
-"""Autotuner of the batched path (row a9).
+"""Autotuner of the batched path.
 
 The tunables of ``group_sweep`` -- band height per lattice size, hipGraph
 capture, dispatch order -- change how the work is laid on the chip, never

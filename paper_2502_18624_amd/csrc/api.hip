@@ -1,6 +1,6 @@
 // C ABI of the library (declared in include/mcl.h): handles, argument
 // checks, host-side acceptance tables and correlation distances, and the
-// plain one-lattice-per-launch sweep driver (row a5).
+// plain one-lattice-per-launch sweep driver.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -205,7 +205,7 @@ void spin_to_cell(uint32_t* row, int64_t i, int s, int cb)
 }
 
 // ---------------------------------------------------------------------------
-// Batched path (row a9).
+// Batched path.
 // ---------------------------------------------------------------------------
 mcl_group_tuning default_tuning()
 {

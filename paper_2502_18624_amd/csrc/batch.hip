@@ -1,4 +1,4 @@
-// Batched half-sweep (row a9): many independent lattices -- any mix of
+// Batched half-sweep: many independent lattices -- any mix of
 // sizes, temperatures, crystal fields and seeds -- advance in one launch per
 // model and colour.  Each workgroup belongs to exactly one replica (its task
 // range is padded to whole workgroups), so the replica's parameters are

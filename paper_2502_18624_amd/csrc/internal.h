@@ -19,10 +19,10 @@ struct Geom {
     int64_t plane_words() const { return L * W; }
 };
 
-// a1: write the initial state into both planes.
+// Write the initial state into both planes.
 hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, hipStream_t s);
 
-// a3 / a4: one colour of one sweep.
+// One colour of one sweep.
 struct HalfSweepArgs {
     int color;
     uint32_t t;
@@ -41,7 +41,7 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, 
                            const void* buckets, hipStream_t s);
 hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
 
-// a6 / a7: measurement kernels accumulating into int64 device scratch.
+// Measurement kernels accumulating into int64 device scratch.
 // acc layout: [0] B, [1] M (from +1 count minus -1 count), [2] #(+1),
 // [3] #(-1), [4] #(0), [5..15] reserved; cells that are none of the three
 // (corrupted) are L^2 minus the three counts.
@@ -67,7 +67,7 @@ struct SampledArgs {
 };
 hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s);
 
-// a9: batched half-sweep.  One descriptor per replica (64 bytes).
+// Batched half-sweep.  One descriptor per replica (64 bytes).
 struct GroupDesc {
     uint32_t* plane0;      // the replica's planes (P_1 follows P_0)
     uint32_t L;

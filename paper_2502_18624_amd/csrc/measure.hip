@@ -1,4 +1,5 @@
-// Measurement kernels for gfx950 (rows a6, a7).
+// Measurement kernels for gfx950: B, M, Q, counts and the Schwinger-Dyson
+// histogram; the correlation sums of section 3.3.
 //
 // Energy-like sums.  Every bond of the periodic lattice joins a colour-0 and
 // a colour-1 site (L even), so the bond sum B is the sum over colour-0 cells
@@ -154,7 +155,7 @@ __device__ __forceinline__ void block_add_xy(const int64_t (&v)[2 * N], int64_t*
 }
 
 // ---------------------------------------------------------------------------
-// a6: B, M, Q, counts.  One thread per 16-byte column of plane 0, walking a
+// B, M, Q, counts.  One thread per 16-byte column of plane 0, walking a
 // band of rows with plane 1's rows y - 1, y, y + 1 in registers.
 // ---------------------------------------------------------------------------
 // Histogram of t = sigma h + 4 (0..8) over the cells of word o, whose four
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// a7, every source, r = 0..R (R <= 32): LDS tile of SW words (+1 halo word
+// Correlations, every source, r = 0..R (R <= 32): LDS tile of SW words (+1 halo word
 // on the right for x-partners) by TH source rows (+32 halo rows below for
 // y-partners), both planes, with the cells as 1-bit words of 32 cells: the
 // sign bit for Ising, and for Blume-Capel a second word of nonzero bits.  A
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// a7, every source, arbitrary r (full mode beyond r = 32): partners read
+// Correlations, every source, arbitrary r (full mode beyond r = 32): partners read
 // from global memory.  One thread per (plane, band of rows, column), a
 // chunk of up to kRChunk distances per grid row.
 // ---------------------------------------------------------------------------
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// a7, sampled sources.  Zs[b * (L / 16) + a] = s(16 a, 16 b) as int8.
+// Correlations, sampled sources.  Zs[b * (L / 16) + a] = s(16 a, 16 b) as int8.
 // ---------------------------------------------------------------------------
 // The source (16 a, 16 b) is in-plane cell 8 a of row 16 b of plane 0.
 template <int CB>

@@ -1,5 +1,5 @@
-// Initial state and the one-lattice half-sweep kernel for gfx950 (rows a1,
-// a3, a4); the per-thread update is in sweep_device.h.
+// Initial state and the one-lattice half-sweep kernels for gfx950; the
+// per-thread update is in sweep_device.h.
 #include <algorithm>
 
 #include "internal.h"
@@ -10,7 +10,7 @@ namespace {
 
 
 // ---------------------------------------------------------------------------
-// a1: initial state.  One thread per 32-bit word (8 cells) of one plane.
+// Initial state.  One thread per 32-bit word (8 cells) of one plane.
 // ---------------------------------------------------------------------------
 // Word g of the two planes (plane-major, then row, then word).
 __device__ __forceinline__ uint32_t init_word(int64_t g, int64_t L, int64_t W, int model, int init_state,
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ 
         dev::band_update<MODEL, 2, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, 0u, T4, T8, s_tab.e);
 }
 
-// a1 for the 1-bit layout: one thread per word (32 cells) of one plane.
+// Initial state of the 1-bit layout: one thread per word (32 cells) of one plane.
 __device__ __forceinline__ uint32_t init1_word(int64_t g, int64_t L, int64_t W, int init_state, uint32_t k0,
                                                uint32_t k1)
 {

@@ -1,6 +1,6 @@
 // Device code of the half-sweep shared by the one-lattice kernel and the
 // batched kernel: acceptance masks, the Ising and Blume-Capel vector
-// updates and the walk of one thread down a band of rows (rows a3, a4).
+// updates and the walk of one thread down a band of rows (Ising and Blume-Capel).
 //
 // A half-sweep updates every cell of colour c (plane P_c) from its four
 // neighbours, which all live in the other plane P_{1-c} (checkerboard
@@ -83,7 +83,7 @@ __device__ __forceinline__ uint32_t horizontal(const uint4& mid, int d, uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// a3: Ising vector update (32 cells).  Cells hold n in {0, 2}; n ^ src is 2
+// Ising vector update (32 cells).  Cells hold n in {0, 2}; n ^ src is 2
 // for a misaligned neighbour, so half the per-nibble sum of the four xors is
 // the number m of misaligned neighbours.  The flip rule of section 3.2
 // (always with at most two aligned neighbours, with probability e^{-4 beta}
@@ -111,7 +111,7 @@ __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, co
 }
 
 // ---------------------------------------------------------------------------
-// a4: Blume-Capel vector update (32 cells).  Per cell: the proposal
+// Blume-Capel vector update (32 cells).  Per cell: the proposal
 // s' = ((n + 1 + b) mod 3) - 1 (n = s + 1, b the proposal bit), then a table
 // lookup on (n, b, sum of neighbour cells) gives E = thr, or 2^32 where
 // dE <= 0, and accept = [u < E].  Word-level: n + 1 + b and its reduction

@@ -1,4 +1,4 @@
-"""Measurement times (row a8, section 3.3).
+"""Measurement times (section 3.3).
 
 The paper measures at t = floor((2^{1/8})^x + 0.5) for positive integers x;
 the benchmark workloads use its x = 0 (mod 8) members, t = 2^k."""

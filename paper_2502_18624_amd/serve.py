@@ -1,4 +1,4 @@
-"""Serving loop (row a10): continuous batching of quench-simulation jobs.
+"""Serving loop: continuous batching of quench-simulation jobs.
 
 A job is (model, L, seed, beta, D, sweeps): a lattice quenched from its T =
 infinity sample and relaxed for `sweeps` checkerboard sweeps, then measured.
