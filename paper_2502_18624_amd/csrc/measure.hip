@@ -679,9 +679,19 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
     const bool live = a0 < NS;                              // NS is a multiple of 4
     const size_t plane_words = (size_t)L * W;
     int acc[kYChunk];
+    // r = rho + 16 m for every distance of this residue: the source row of
+    // target row rho + 16 k is k - m (mod L / 16, a power of two).  The shifts
+    // m live in registers, so the 32 source loads of a target row are
+    // independent; slots past the list use m = 0 and are discarded.
+    uint32_t msh[kYChunk];
 #pragma unroll
-    for (int k = 0; k < kYChunk; ++k) acc[k] = 0;
-    const uint32_t nrows = L >> 4;                          // target rows per residue
+    for (int k = 0; k < kYChunk; ++k) {
+        acc[k] = 0;
+        const int p = p0 + k;
+        msh[k] = p < p1 ? ((uint32_t)rlist[res_idx[p]] - rho) >> 4 : 0u;
+    }
+    const uint32_t nrows = L >> 4;                          // target rows per residue, and source rows
+    const int8_t* zcol = zs + a0;
     for (uint32_t kk = 0; kk < kYRows; ++kk) {
         const uint32_t krow = band * kYRows + kk;
         if (krow >= nrows || !live) break;
@@ -698,19 +708,15 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
         } else {
             // cells 8 a0 .. 8 a0 + 24 are bits 0, 8, 16, 24 of word a0 / 4;
             // byte = bit ? 0x01 : 0xFF (no carries between bytes)
-            const uint32_t tw = trow[a0 >> 2] & 0x01010101u;
-            tp = (int)(tw | ((tw ^ 0x01010101u) * 0xFFu));
+            const uint32_t tw = trow[a0 >> 2] & 0x01010101u, nw = tw ^ 0x01010101u;
+            tp = (int)(tw | (shl_opaque<8>(nw) - nw));
         }
+        int sp[kYChunk];
 #pragma unroll
-        for (int k = 0; k < kYChunk; ++k) {
-            const int p = p0 + k;
-            if (p < p1) {
-                const uint32_t r = (uint32_t)rlist[res_idx[p]];
-                const uint32_t ys = wrap(yt + L - r, L);    // source row 16 b
-                const int sp = *reinterpret_cast<const int*>(zs + (size_t)(ys >> 4) * NS + a0);
-                acc[k] = __builtin_amdgcn_sdot4(sp, tp, acc[k], false);
-            }
-        }
+        for (int k = 0; k < kYChunk; ++k)
+            sp[k] = *reinterpret_cast<const int*>(zcol + (size_t)((krow - msh[k]) & (nrows - 1)) * NS);
+#pragma unroll
+        for (int k = 0; k < kYChunk; ++k) acc[k] = __builtin_amdgcn_sdot4(sp[k], tp, acc[k], false);
     }
     __shared__ int red[4][kYChunk];
     const int wave = threadIdx.x >> 6;
