@@ -587,53 +587,75 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
                                                       const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
                                                       uint32_t G, int64_t* __restrict__ Cx)
 {
-    extern __shared__ int sx_lds[];                 // nr int32 sums, R_0, then R_rho0 .. R_{rho0+G-1}
+    // LDS: nr int32 sums, the nr distances, R_0, then R_rho0 .. R_{rho0+G-1}
+    extern __shared__ int sx_lds[];
     int* sums = sx_lds;
+    int* rl = sx_lds + nr;
     const uint32_t W = L >> Cell<CB>::kWordShift;
     const uint32_t P = L >> 4;                      // bytes per residue class
     const uint32_t PQ = P >> 2;                     // words per residue class (a power of two)
-    int8_t* zrow = reinterpret_cast<int8_t*>(sx_lds + nr);
+    int8_t* zrow = reinterpret_cast<int8_t*>(sx_lds + 2 * nr);
     int8_t* grow = zrow + P;
     const uint32_t* zrow_w = reinterpret_cast<const uint32_t*>(zrow);
     const uint32_t* grow_w = reinterpret_cast<const uint32_t*>(grow);
-    const size_t plane_words = (size_t)L * W;
+    const size_t plane_vecs = (size_t)L * (W >> 2);
+    const uint4* P4 = reinterpret_cast<const uint4*>(planes);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
-    for (int k = threadIdx.x; k < nr; k += blockDim.x) sums[k] = 0;
+    for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+        sums[k] = 0;
+        rl[k] = rlist[k];
+    }
     for (uint32_t b = blockIdx.x; b < (L >> 4); b += gridDim.x) {
         const uint32_t y = 16 * b;
         __syncthreads();
-        for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
-            const uint32_t c = idx >= W ? 1u : 0u;
-            const uint32_t wd = idx - c * W;
-            const uint32_t word = planes[c * plane_words + (size_t)y * W + wd];
+        // 16-byte vectors of both plane rows (W is a multiple of 4)
+        for (uint32_t idx = threadIdx.x; idx < (W >> 1); idx += blockDim.x) {
+            const uint32_t c = idx >= (W >> 2) ? 1u : 0u;
+            const uint32_t v4 = idx - c * (W >> 2);
+            const uint4 v = P4[c * plane_vecs + (size_t)y * (W >> 2) + v4];
             const uint32_t par = (y + c) & 1u;              // x = 2 i + par
 #pragma unroll
-            for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
-                const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
-                const int8_t sv = (int8_t)(CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1
-                                                   : (((word >> k) & 1u) ? 1 : -1));
-                const uint32_t rho = x & 15u, a = x >> 4;
-                if (rho == 0) zrow[a] = sv;
-                if (rho - rho0 < G) grow[(rho - rho0) * P + a] = sv;
+            for (int d = 0; d < 4; ++d) {
+                const uint32_t word = pick(v, d);
+                const uint32_t wd = 4 * v4 + d;
+#pragma unroll
+                for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
+                    const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
+                    const int8_t sv = (int8_t)(CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1
+                                                       : (((word >> k) & 1u) ? 1 : -1));
+                    const uint32_t rho = x & 15u, a = x >> 4;
+                    if (rho == 0) zrow[a] = sv;
+                    if (rho - rho0 < G) grow[(rho - rho0) * P + a] = sv;
+                }
             }
         }
         __syncthreads();
         for (int k = wave; k < nr; k += nwaves) {
-            const uint32_t r = (uint32_t)rlist[k];
+            const uint32_t r = (uint32_t)rl[k];
             if ((r & 15u) - rho0 >= G) continue;            // another pass's residue
             const uint32_t base = ((r & 15u) - rho0) * PQ;
             const uint32_t sh = r >> 4;                     // whole sources of offset
             const uint32_t qs = sh >> 2, bs = sh & 3u;
-            int acc = 0;
-            for (uint32_t q = lane; q < PQ; q += 64) {
-                const uint32_t wi = (q + qs) & (PQ - 1);
-                const uint32_t lo = grow_w[base + wi];
-                const uint32_t hi = grow_w[base + ((wi + 1) & (PQ - 1))];
-                const uint32_t part = __builtin_amdgcn_alignbyte(hi, lo, bs);
-                acc = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)part, acc, false);
+            // quads q < PQ - 1 - qs read words q + qs and q + qs + 1 without wrapping:
+            // plain offsets, two quads (q, q + 64) per step; the rest wraps mod PQ
+            const uint32_t qlim = PQ - 1 - qs;
+            const uint32_t* gb = grow_w + base + qs;
+            int acc0 = 0, acc1 = 0;
+            uint32_t q = lane;
+            for (; q + 64 < qlim; q += 128) {
+                acc0 = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)__builtin_amdgcn_alignbyte(gb[q + 1], gb[q], bs),
+                                              acc0, false);
+                acc1 = __builtin_amdgcn_sdot4((int)zrow_w[q + 64],
+                                              (int)__builtin_amdgcn_alignbyte(gb[q + 65], gb[q + 64], bs), acc1, false);
             }
-            const int s2 = wave_sum_i32(acc);
+            for (; q < PQ; q += 64) {
+                const uint32_t wi = (q + qs) & (PQ - 1);
+                const uint32_t part = __builtin_amdgcn_alignbyte(grow_w[base + ((wi + 1) & (PQ - 1))],
+                                                                 grow_w[base + wi], bs);
+                acc0 = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)part, acc0, false);
+            }
+            const int s2 = wave_sum_i32(acc0 + acc1);
             if (lane == 0) sums[k] += s2;
         }
     }
@@ -830,14 +852,15 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     // and a group of G residue rows (P = L / 16 bytes each)
     const size_t P = nb, budget = sx_lds_budget();
     const uint32_t gx = std::min<uint32_t>(nb, 512);
+    // 8 bytes per distance (its sum and its value)
     uint32_t G = 16;
-    while (G > 1 && 4u * 64u + P * (1 + G) > budget) G >>= 1;
-    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(P * (1 + G))) / 4));
-    if (P * (1 + G) + 4 > budget) return hipErrorInvalidValue;
+    while (G > 1 && 8u * 64u + P * (1 + G) > budget) G >>= 1;
+    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(P * (1 + G))) / 8));
+    if (P * (1 + G) + 8 > budget) return hipErrorInvalidValue;
     static size_t attr_bytes = 0;
     for (int j0 = 0; j0 < a.nr; j0 += max_r) {
         const int nr = std::min(max_r, a.nr - j0);
-        const size_t lds = (size_t)nr * 4 + P * (1 + G);
+        const size_t lds = (size_t)nr * 8 + P * (1 + G);
         if (lds > 64u * 1024u && attr_bytes < lds) {
             e = hipFuncSetAttribute((const void*)corr_sx_kernel<CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds);
