@@ -344,11 +344,8 @@ def run(args):
     lat = mcl.Lattice(mcl.ISING, L, seed, stream=stream, mem=mem)   # quench restarts at t = 0
     torch.cuda.synchronize()
 
-    marks = []
-    t = 1
-    while t <= args.steps:
-        marks.append(t)
-        t *= 2
+    from paper_2502_18624_amd.schedule import paper_times, pow2_times
+    marks = paper_times(args.steps) if args.schedule == "paper" else pow2_times(args.steps)
     ev = []
     measures = []
     t_meas = 0.0
@@ -399,7 +396,8 @@ def run(args):
         "dtype": "u4 cells, u32 Philox draws (integer path)",
         "data": "synthetic (seeded Philox4x32-10 random start)",
         "config": {"workload": "Ising quench, L=2^17, T=T_c, random +-1 start, %d sweeps, protocol C(r,t) and "
-                               "B/M at t=2^k, one lattice per launch" % args.steps,
+                               "B/M at %s, one lattice per launch" % (
+                                   args.steps, "t=floor(2^(x/8)+0.5)" if args.schedule == "paper" else "t=2^k"),
                    "L": L, "seed": seed, "beta": beta, "measure_times": marks},
         "sweep_only_updates_per_ns": round(updates / (sweep_ms * 1e6), 2),
         "measure_share": round(t_meas / wall, 4),
@@ -427,6 +425,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--L", type=int, default=2 ** 17)
+    ap.add_argument("--schedule", choices=("pow2", "paper"), default="pow2",
+                    help="measurement times of the headline quench: t = 2^k, or the paper's floor(2^(x/8) + 0.5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
     ap.add_argument("--extras", default="bc,lut,batched,serving,scan",
