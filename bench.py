@@ -53,9 +53,14 @@ def cpu_baseline(budget_s=12.0):
         el = time.perf_counter() - t0
         if el > budget_s or done >= 16:
             break
+    # the same sample on one thread (two more sweeps)
+    t1 = time.perf_counter()
+    oracle.sweep(s, oracle.ISING, 1002, done, 2, BETA_C, 0.0, nthreads=1)
+    el1 = time.perf_counter() - t1
     return {"value": round(L * L * done / (el * 1e9), 5), "unit": "updates/ns", "cores": cores, "kind": "oracle",
             "sample": "Ising L=2^13 at T_c from a random start, %d sweeps (%.1f s), rows of one colour split over "
-                      "%d OpenMP threads" % (done, el, cores)}
+                      "%d OpenMP threads" % (done, el, cores),
+            "single_thread_value": round(L * L * 2 / (el1 * 1e9), 5)}
 
 
 def kernel_source_sha():

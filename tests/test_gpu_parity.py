@@ -242,3 +242,20 @@ def test_sampled_x_correlation_in_residue_passes(mcl, monkeypatch, budget, model
     m = lat.measure(mcl.CORR_PROTOCOL)
     Cx, Cy, ns = oracle.corr(s, oracle.CORR_PROTOCOL, m["r"])
     assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy)
+
+
+def test_lattices_on_separate_streams(mcl):
+    """Independent handles on their own streams, their sweeps queued
+    interleaved and running concurrently: each ends equal to the oracle."""
+    import torch
+    print("separate streams", flush=True)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    specs = [(0, 512, 61, BETA_C, 0.0), (1, 256, 62, 1 / 1.4, 1.0), (2, 512, 63, BETA_C / 0.9, 0.0)]
+    lats = [mcl.Lattice(m, L, sd, stream=st) for (m, L, sd, _, _), st in zip(specs, streams)]
+    for _ in range(3):
+        for lat, (m, L, sd, b, D) in zip(lats, specs):
+            lat.sweep(2, b, D)
+    torch.cuda.synchronize()
+    for lat, (m, L, sd, b, D) in zip(lats, specs):
+        assert lat.t == 6
+        assert np.array_equal(lat.read(), _oracle_run(m, L, sd, 0, 6, b, D)), m
