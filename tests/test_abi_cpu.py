@@ -171,3 +171,19 @@ def test_schwinger_dyson_helper_equals_site_average(mcl, model, beta):
     assert mcl.schwinger_dyson(oracle.sd_hist(up), beta) == pytest.approx(math.exp(-8 * beta), rel=1e-15)
     with pytest.raises(ValueError):
         mcl.schwinger_dyson([0] * 9, beta)
+
+
+def test_header_is_plain_c_and_cpp(tmp_path):
+    """include/mcl.h compiles as strict C99 and as C++ (no torch or HIP types
+    in its signatures)."""
+    src = tmp_path / "h.c"
+    src.write_text('#include "mcl.h"\nint main(void) { mcl_measure_out o = {0}; return (int)o.n_r; }\n')
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc, str(src)],
+                   check=True)
+    subprocess.run(["g++", "-x", "c++", "-Wall", "-Werror", "-fsyntax-only", "-I", inc, str(src)], check=True)
+
+
+def test_c_program_builds_against_the_abi(mcl, tmp_path):
+    from tests import c_abi
+    assert os.path.exists(c_abi.build(str(tmp_path / "q")))
