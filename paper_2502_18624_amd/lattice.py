@@ -63,6 +63,18 @@ def schwinger_dyson(sd, beta: float) -> float:
     return math.fsum(int(v) * math.exp(-2.0 * beta * (k - 4)) for k, v in enumerate(sd) if v) / n
 
 
+def energy(m: dict, D: float = 0.0) -> int | float:
+    """E = -B + D Q from a measurement (J = 1; eq. IM for Ising, eq. BC)."""
+    return -m["B"] + D * m["Q"] if D else -m["B"]
+
+
+def correlation(m: dict):
+    """Normalised correlations C_x(r) = S_x(r) / nsrc(r), C_y(r) likewise,
+    from a measurement taken with a correlation mode (float64 arrays)."""
+    ns = np.asarray(m["nsrc"], dtype=np.float64)
+    return np.asarray(m["Cx"]) / ns, np.asarray(m["Cy"]) / ns
+
+
 class Lattice:
     """One L x L lattice resident in HBM (two 4-bit colour planes)."""
 

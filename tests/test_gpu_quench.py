@@ -1,0 +1,58 @@
+"""The quench driver: measurements at the schedule times equal the oracle's
+lattice evolved to the same t, through the library's own entry points."""
+import json
+import math
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = math.log(1 + math.sqrt(2)) / 2
+
+
+@pytest.fixture(scope="module")
+def mcl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_18624_amd as m
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("model,D,schedule", [(0, 0.0, "paper"), (1, 1.0, "pow2"), (2, 0.0, "pow2")])
+def test_run_quench_equals_oracle(mcl, model, D, schedule):
+    from paper_2502_18624_amd.quench import run_quench
+    from paper_2502_18624_amd.schedule import paper_times, pow2_times
+    L, seed, n, beta = 256, 41, 40, (BETA_C if model != 1 else 1 / 1.4)
+    times = paper_times(n) if schedule == "paper" else pow2_times(n)
+    s = oracle.init(model, L, seed)
+    t = 0
+    got = list(run_quench(model, L, seed, beta, D, n, schedule))
+    assert [m["t"] for m in got] == times
+    for m in got:
+        oracle.sweep(s, model, seed, t, m["t"] - t, beta, D)
+        t = m["t"]
+        om = oracle.measure(s)
+        assert (m["B"], m["M"], m["Q"]) == (om["B"], om["M"], om["Q"])
+        assert m["E"] == -om["B"] + D * om["Q"]
+        Cx, Cy, ns = oracle.corr(s, oracle.CORR_PROTOCOL, m["r"])
+        assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy)
+        assert np.allclose(m["Cx_norm"], Cx / ns) and m["Cx_norm"][0] == m["Q"] / L**2     # C(0) = Q / N
+        assert m["schwinger_dyson"] == mcl.schwinger_dyson(oracle.sd_hist(s), beta)
+
+
+def test_quench_command_line(mcl, tmp_path):
+    out = tmp_path / "q.jsonl"
+    subprocess.run([sys.executable, "-m", "paper_2502_18624_amd.quench", "--model", "blume-capel", "--L", "128",
+                    "--beta", "0.7", "--D", "0.5", "--sweeps", "8", "--out", str(out)], check=True, timeout=300)
+    rows = [json.loads(x) for x in out.read_text().splitlines()]
+    assert [r["t"] for r in rows] == [1, 2, 4, 8]
+    s = oracle.init(1, 128, 1)
+    oracle.sweep(s, 1, 1, 0, 8, 0.7, 0.5)
+    assert rows[-1]["B"] == oracle.measure(s)["B"]
