@@ -857,15 +857,14 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     while (G > 1 && 8u * 64u + P * (1 + G) > budget) G >>= 1;
     const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(P * (1 + G))) / 8));
     if (P * (1 + G) + 8 > budget) return hipErrorInvalidValue;
-    static size_t attr_bytes = 0;
     for (int j0 = 0; j0 < a.nr; j0 += max_r) {
         const int nr = std::min(max_r, a.nr - j0);
         const size_t lds = (size_t)nr * 8 + P * (1 + G);
-        if (lds > 64u * 1024u && attr_bytes < lds) {
+        // the attribute belongs to the current device: set it for every launch that needs it
+        if (lds > 64u * 1024u) {
             e = hipFuncSetAttribute((const void*)corr_sx_kernel<CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds);
             if (e != hipSuccess) return e;
-            attr_bytes = lds;
         }
         for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
             hipLaunchKernelGGL((corr_sx_kernel<CB>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr, rho0, G,
