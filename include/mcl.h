@@ -130,10 +130,15 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
  * Asynchronous on the handle's stream; advances t by n. */
 int sweep(mcl_lattice* h, int64_t n, double beta, double D);
 
-/* B, M, Q, spin counts and, if corr_mode != NONE, the
- * correlation sums along both axes at the distances of the mode for the
- * current t (section 3.3).  Synchronous.  MCL_EBUFSZ if r_cap < needed
- * (out->n_r then holds the needed size). */
+/* B, M, Q, spin counts, the sigma h histogram (out->sd) and, if corr_mode !=
+ * NONE, the correlation sums along both axes at the distances of the mode
+ * for the current t (section 3.3).  Synchronous (waits for the handle's
+ * stream, so it must not be captured into a graph).  MCL_EBUFSZ if r_cap <
+ * needed (out->n_r then holds the needed size); MCL_EL for the protocol mode
+ * with L not a power of two.  The x-correlation of the sampled sources keeps
+ * rows in LDS; the environment variable MCL_SX_LDS_BUDGET (bytes, read at
+ * every call) lowers its budget below the 160 KiB of a workgroup, which
+ * changes the launch shape only, never the result. */
 int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out);
 
 /* Distances measure() would use for (mode, L, t); returns their number or
