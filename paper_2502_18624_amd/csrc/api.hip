@@ -313,7 +313,7 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
         // graphs captured against the old device buffer are dropped with it
         for (auto it = g_graphs.begin(); it != g_graphs.end();) {
             if (std::get<0>(it->first) == sl.dev) {
-                hipGraphExecDestroy(it->second);
+                (void)hipGraphExecDestroy(it->second);          // best effort: the buffer goes with it
                 it = g_graphs.erase(it);
             } else {
                 ++it;
@@ -404,13 +404,14 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
                     for (int m = 0; m < 2 && le == hipSuccess; ++m)
                         le = mcl::launch_group_half(m, c, ddesc[m], cnt[m], wgs[m], dtab, (uint32_t)s, gs);
             const hipError_t ce = hipStreamEndCapture(gs, &graph);
+            if (ce == hipSuccess && le != hipSuccess) (void)hipGraphDestroy(graph);
             if (le != hipSuccess) return hip_fail(le);
             if (ce != hipSuccess) return hip_fail(ce);
             const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);                       // the executable graph keeps what it needs
             if (ie != hipSuccess) return hip_fail(ie);
             if (g_graphs.size() >= 32) {
-                hipGraphExecDestroy(g_graphs.begin()->second);
+                (void)hipGraphExecDestroy(g_graphs.begin()->second);
                 g_graphs.erase(g_graphs.begin());
             }
             it = g_graphs.emplace(key, exec).first;
