@@ -5,7 +5,6 @@ import math
 import os
 import subprocess
 
-import numpy as np
 import pytest
 
 import oracle

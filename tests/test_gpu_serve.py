@@ -5,7 +5,6 @@ the same results."""
 import hashlib
 import math
 
-import numpy as np
 import pytest
 
 import oracle
