@@ -319,7 +319,8 @@ def run_serving(args):
             rate = 0.7 * cap / mean_work
         jobs = poisson_trace(args.serve_jobs, rate_per_s=rate, seed=4)
         mean_work = sum(j.updates for j in jobs) / len(jobs)
-        srv = Server(hbm_budget=250e9, tick_seconds=0.02)
+        # no result digests here: they copy each finished lattice to the host (a test aid)
+        srv = Server(hbm_budget=250e9, tick_seconds=0.02, keep_digest=False)
         st = srv.run_trace(jobs)
         st["rate_per_s"] = round(rate, 3)
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
