@@ -110,7 +110,7 @@ typedef struct mcl_measure_out {
 
 /* Device bytes lattice_init() needs for an L x L lattice of `model`: two
  * colour planes of 4-bit cells (L^2 / 2 bytes; L^2 / 8 for 1-bit cells)
- * plus measurement scratch. */
+ * plus measurement scratch and a 256-byte control block. */
 int mcl_query_bytes(int model, int64_t L, int64_t* dev_bytes);
 
 /* Create a handle and write the initial state (section 1: quench
@@ -127,7 +127,15 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
  * otherwise always (section 3.2).  Blume-Capel: the proposal is one of the
  * two other values, chosen by the proposal bit (0: next value cyclically in
  * -1,0,+1; 1: the one after), accepted by Metropolis on eq. (BC).
- * Asynchronous on the handle's stream; advances t by n. */
+ * Asynchronous on the handle's stream; advances t by n.
+ * Lattices of up to 2^24 cells run calls of 32 sweeps or more as replays of
+ * an executable HIP graph of 32 sweeps, captured on first use for each
+ * (beta, D) (up to four per handle, destroyed by lattice_free) on a
+ * library stream of default priority; the sweep index then comes from a
+ * word of the handle's device buffer.  The lattices are the same either
+ * way.  The environment variable MCL_SWEEP_GRAPH=0 (never) or 1 (at any
+ * size) overrides the size rule; it is read on each call.  Errors: MCL_EARG
+ * (n < 0), MCL_EBETA, MCL_ED, MCL_ERANGE (t + n > 2^32), MCL_EHIP. */
 int sweep(mcl_lattice* h, int64_t n, double beta, double D);
 
 /* B, M, Q, spin counts, the sigma h histogram (out->sd) and, if corr_mode !=
@@ -209,7 +217,9 @@ typedef struct mcl_group_tuning {
 int mcl_group_tuning_get(mcl_group_tuning* out);
 int mcl_group_tuning_set(const mcl_group_tuning* in);   /* MCL_EARG on an invalid row count */
 
-/* Release a handle (does not free the caller's device memory). */
+/* Release a handle (does not free the caller's device memory).  A handle
+ * whose sweeps were replayed from graphs first waits for its stream, then
+ * destroys the graphs. */
 int lattice_free(mcl_lattice* h);
 
 const char* mcl_strerror(int code);

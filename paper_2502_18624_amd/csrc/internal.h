@@ -25,7 +25,8 @@ hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, 
 // One colour of one sweep.
 struct HalfSweepArgs {
     int color;
-    uint32_t t;
+    uint32_t t;             // sweep index, or its offset from *tbase when tbase is set
+    const uint32_t* tbase;  // device word added to t by the kernel (nullptr: t is absolute)
     uint64_t seed;
     uint32_t T4, T8;        // Ising thresholds (e^{-4 beta}, e^{-8 beta})
     const BCTable* bc;      // Blume-Capel table (host copy, passed by value)
@@ -37,9 +38,12 @@ hipError_t launch_init1(const Geom& g, int init_state, uint64_t seed, hipStream_
 // once per beta, read by every half-sweep at that beta.
 constexpr int64_t kLutBucketBytes = 4096 * 8;
 hipError_t launch_lut_buckets(const LutTable& tab, void* buckets, hipStream_t s);
-hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab,
-                           const void* buckets, hipStream_t s);
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, const uint32_t* tbase, uint64_t seed,
+                           const LutTable& tab, const void* buckets, hipStream_t s);
 hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s);
+// One device word: *p = v, or *p += v with add (a one-lane kernel, so that
+// it can sit in a captured graph).
+hipError_t launch_set_word(uint32_t* p, uint32_t v, bool add, hipStream_t s);
 
 // Measurement kernels accumulating into int64 device scratch.
 // acc layout: [0] B, [1] M (from +1 count minus -1 count), [2] #(+1),

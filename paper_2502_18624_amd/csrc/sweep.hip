@@ -57,12 +57,16 @@ __global__ __launch_bounds__(256) void init_kernel(uint32_t* __restrict__ planes
         planes[g] = init_word(g, L, W, model, init_state, k0, k1);
 }
 
+// The sweep index of a launch is t, plus the device word *tbase when tbase
+// is given (a captured graph replays the same launches at any starting t).
 template <int MODEL, bool HI0, int COLOR>
 __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
-                                                         uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
+                                                         uint32_t L, uint32_t rows, uint32_t t,
+                                                         const uint32_t* __restrict__ tbase, uint32_t k0,
                                                          uint32_t k1, uint32_t T4, uint32_t T8, BCTable tbl)
 {
     __shared__ dev::BCLds s_tab;
+    if (tbase) t += *tbase;
     if (MODEL == 1) dev::load_bc_table(s_tab, tbl);
     const uint32_t Q = L >> 6;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,9 +146,11 @@ __global__ __launch_bounds__(256) void lut_bucket_kernel(LutTable tab, uint2* __
 
 template <bool HI0, int COLOR>
 __global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
-                                                       uint32_t L, uint32_t rows, uint32_t t, uint32_t k0,
-                                                       uint32_t k1, LutTable tab, const uint2* __restrict__ buckets)
+                                                       uint32_t L, uint32_t rows, uint32_t t,
+                                                       const uint32_t* __restrict__ tbase, uint32_t k0, uint32_t k1,
+                                                       LutTable tab, const uint2* __restrict__ buckets)
 {
+    if (tbase) t += *tbase;
     __shared__ uint32_t s_lut[16];
     __shared__ uint2 s_b[dev::kLutBuckets];
     if (threadIdx.x < 16) s_lut[threadIdx.x] = tab.T[threadIdx.x];
@@ -199,14 +205,15 @@ hipError_t launch_init(const Geom& g, int model, int init_state, uint64_t seed, 
 
 template <int MODEL, bool HI0>
 static void launch_model(dim3 grid, hipStream_t s, uint32_t* own, const uint32_t* oth, uint32_t L, uint32_t R, int c,
-                         uint32_t t, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8, const BCTable& tbl)
+                         uint32_t t, const uint32_t* tbase, uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8,
+                         const BCTable& tbl)
 {
     if (c == 0)
-        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, T4,
-                           T8, tbl);
+        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0,
+                           k1, T4, T8, tbl);
     else
-        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, T4,
-                           T8, tbl);
+        hipLaunchKernelGGL((half_sweep_kernel<MODEL, HI0, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0,
+                           k1, T4, T8, tbl);
 }
 
 static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s, int model)
@@ -224,11 +231,11 @@ static hipError_t launch_half(const Geom& g, const HalfSweepArgs& a, hipStream_t
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
     const dim3 grid((uint32_t)blocks);
     if (model == 0) {
-        if (hi0) launch_model<0, true>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
-        else launch_model<0, false>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+        if (hi0) launch_model<0, true>(grid, s, own, oth, L, R, a.color, a.t, a.tbase, k0, k1, a.T4, a.T8, tbl);
+        else launch_model<0, false>(grid, s, own, oth, L, R, a.color, a.t, a.tbase, k0, k1, a.T4, a.T8, tbl);
     } else {
-        if (hi0) launch_model<1, true>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
-        else launch_model<1, false>(grid, s, own, oth, L, R, a.color, a.t, k0, k1, a.T4, a.T8, tbl);
+        if (hi0) launch_model<1, true>(grid, s, own, oth, L, R, a.color, a.t, a.tbase, k0, k1, a.T4, a.T8, tbl);
+        else launch_model<1, false>(grid, s, own, oth, L, R, a.color, a.t, a.tbase, k0, k1, a.T4, a.T8, tbl);
     }
     return hipGetLastError();
 }
@@ -249,8 +256,8 @@ hipError_t launch_lut_buckets(const LutTable& tab, void* buckets, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, const LutTable& tab,
-                           const void* buckets, hipStream_t s)
+hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, const uint32_t* tbase, uint64_t seed,
+                           const LutTable& tab, const void* buckets, hipStream_t s)
 {
     const uint2* bk = reinterpret_cast<const uint2*>(buckets);
     const int64_t rows = band_rows(g.Q, g.L);
@@ -263,16 +270,40 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, uint64_t seed, 
     // group blocks (in-colour index / 16) fit 32 bits while L^2 / 32 <= 2^32
     const bool hi0 = (g.L * g.L / 32) <= (int64_t(1) << 32);
     if (hi0) {
-        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
-        else hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
+        if (color == 0)
+            hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+                               tab, bk);
+        else
+            hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+                               tab, bk);
     } else {
-        if (color == 0) hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
-        else hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, k0, k1, tab, bk);
+        if (color == 0)
+            hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+                               tab, bk);
+        else
+            hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+                               tab, bk);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_ising_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s) { return launch_half(g, a, s, 0); }
 hipError_t launch_bc_half(const Geom& g, const HalfSweepArgs& a, hipStream_t s) { return launch_half(g, a, s, 1); }
+
+namespace {
+
+// One lane stores (vector store): *p = v, or *p += v.
+__global__ void set_word_kernel(uint32_t* p, uint32_t v, int add)
+{
+    if (threadIdx.x == 0) *p = add ? *p + v : v;
+}
+
+}  // namespace
+
+hipError_t launch_set_word(uint32_t* p, uint32_t v, bool add, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_word_kernel, dim3(1), dim3(64), 0, s, p, v, add ? 1 : 0);
+    return hipGetLastError();
+}
 
 }  // namespace mcl
