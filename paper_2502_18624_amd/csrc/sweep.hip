@@ -179,12 +179,15 @@ __global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ ow
 
 // Band height (rows per thread, even, dividing L): 32 amortises the two
 // halo rows of the other plane (1/16 extra reads); smaller lattices take
-// shorter bands so that a launch still has about 2048 waves (8 per CU) --
-// Q vectors per row, L rows.
+// shorter bands until a launch has 2^20 threads (16 waves per SIMD) --
+// Q vectors per row, L rows.  Measured against targets of 2^17 to 2^22
+// threads: 2^20 is the best or within 1% at every L, and up to 26% faster
+// than 2^17 at L = 2^13..2^15 (other waves hide the latency of each
+// thread's chain of row steps); L >= 2^16 (4-bit) keeps 32 rows either way.
 int64_t band_rows(int64_t Q, int64_t L)
 {
     int64_t rows = 32;
-    while (rows > 2 && Q * (L / rows) < 131072) rows >>= 1;
+    while (rows > 2 && Q * (L / rows) < (int64_t(1) << 20)) rows >>= 1;
     return rows;
 }
 

@@ -259,3 +259,39 @@ def test_lattices_on_separate_streams(mcl):
     for lat, (m, L, sd, b, D) in zip(lats, specs):
         assert lat.t == 6
         assert np.array_equal(lat.read(), _oracle_run(m, L, sd, 0, 6, b, D)), m
+
+
+def _band_rows(model, L):
+    """Rows per thread of the plain half-sweep: 32, halved (down to 2)
+    until a launch has 2^20 threads; a thread owns one 16-byte column."""
+    Q = L // (256 if model == 2 else 64)
+    rows = 32
+    while rows > 2 and Q * (L // rows) < 2**20:
+        rows //= 2
+    return rows
+
+
+# sizes at which the plain sweep takes each band height, both cell widths
+BAND_CASES = [(0, 2**13, 2), (1, 2**14, 4), (0, 24576, 8), (1, 2**15, 16), (2, 2**15, 4), (2, 49152, 8),
+              (2, 2**16, 16)]
+
+
+@pytest.mark.parametrize("model,L,rows", BAND_CASES)
+def test_band_heights(mcl, model, L, rows):
+    """Light-cone windows straddling band boundaries (first, middle and
+    last band, both horizontal wraps) after 3 sweeps, against the oracle."""
+    assert _band_rows(model, L) == rows
+    print("band heights", model, L, rows, flush=True)
+    n, seed = 3, 2201 + model
+    beta, D = (1 / 1.4, 1.0) if model == 1 else (BETA_C, 0.0)
+    lat = mcl.Lattice(model, L, seed)
+    lat.sweep(n, beta, D)
+    W, pad = 32, 2 * n
+    P = W + 2 * pad
+    ys = [L - W // 2, rows * (L // rows // 2) - W // 2, L - rows - W // 2]
+    for y0 in ys:
+        for x0 in (0, L // 3, L - 16):
+            got = lat.read_window(x0, y0 % L, W, W)
+            patch = oracle.window_run(model, L, seed, (x0 - pad) % L, (y0 - pad) % L, P, n, beta, D)
+            assert np.array_equal(got, patch[pad:pad + W, pad:pad + W]), (x0, y0)
+    lat.free()
