@@ -134,7 +134,11 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
  * library stream of default priority; the sweep index then comes from a
  * word of the handle's device buffer.  The lattices are the same either
  * way.  The environment variable MCL_SWEEP_GRAPH=0 (never) or 1 (at any
- * size) overrides the size rule; it is read on each call.  Errors: MCL_EARG
+ * size) overrides the size rule; it is read on each call.  While the
+ * caller captures the handle's stream into a graph of its own, sweep()
+ * queues plain launches, which carry absolute sweep indices: each replay of
+ * the caller's graph repeats the same t values (t advances once, when the
+ * call is captured).  Errors: MCL_EARG
  * (n < 0), MCL_EBETA, MCL_ED, MCL_ERANGE (t + n > 2^32), MCL_EHIP. */
 int sweep(mcl_lattice* h, int64_t n, double beta, double D);
 

@@ -485,6 +485,10 @@ constexpr int64_t kGraphMaxCells = int64_t(1) << 24;   // L <= 2^12
 
 bool use_sweep_graph(const mcl_lattice* h)
 {
+    // a stream that the caller is capturing gets plain launches: no graph
+    // of the library's own is captured or launched inside the caller's
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
     if (const char* e = std::getenv("MCL_SWEEP_GRAPH")) {
         if (e[0] == '0') return false;
         if (e[0] == '1') return true;

@@ -4,7 +4,8 @@ against the oracle, bit for bit: one call spanning several replays and a
 remainder, calls split at arbitrary points, changes of temperature between
 calls (new graphs, cached graphs, and more temperatures than the cache
 holds), a restore at an arbitrary t up to the end of the sweep counter,
-lattices on separate streams, and the replay switched off and on."""
+lattices on separate streams, the replay switched off and on, and a caller
+that captures sweep() into a graph of its own."""
 import math
 
 import numpy as np
@@ -149,3 +150,31 @@ def test_free_with_replays_queued_then_reuse(mcl, replay):
     b.sweep(64, beta)
     assert np.array_equal(b.read(), _oracle(0, L, 2162, [(64, beta, 0.0)]))
     b.free()
+
+
+@pytest.mark.parametrize("model", [0, 2])
+def test_caller_captures_sweeps(mcl, replay, model):
+    """A caller captures 40 sweeps of a handle on its own stream into a
+    torch CUDA graph (sweep() then queues plain launches, even with the
+    replay forced on) and replays it three times, with eager work and a
+    synchronisation between replays: each replay repeats sweeps t = 0..39
+    and matches the oracle applied to the previous state."""
+    import torch
+    print("graph: caller capture", model, flush=True)
+    L, seed = 256, 2171 + model
+    beta, D = PARAMS[model]
+    st = torch.cuda.Stream()
+    lat = mcl.Lattice(model, L, seed, stream=st)
+    want = lat.read()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        lat.sweep(40, beta, D)
+    assert lat.t == 40
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        want = _oracle(model, L, seed, [(40, beta, D)], start=want)
+        assert np.array_equal(lat.read(), want), k
+        x = torch.ones(4096, device="cuda")
+        assert float((x + 1.0).sum()) == 8192.0             # eager work between replays
