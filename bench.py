@@ -99,19 +99,31 @@ def measured_valu_busy(name):
     return None if k is None or "valu_busy" not in k else round(k["valu_busy"], 3)
 
 
-def attainable_copy():
-    """Copy-kernel bandwidth from the calibration program (GB/s), or None."""
-    import re
+def _calibrate(mode):
+    """Output of the calibration program in one mode ("copy" or "philox"), or ""."""
     import subprocess
     exe = os.path.join(ROOT, "paper_2502_18624_amd", "mcl_calibrate")
     if not os.path.exists(exe):
-        return None
+        return ""
     try:
-        out = subprocess.run([exe, "copy"], capture_output=True, text=True, timeout=60).stdout
+        return subprocess.run([exe, mode], capture_output=True, text=True, timeout=60).stdout
     except (OSError, subprocess.SubprocessError):
-        return None
-    vals = [float(v) for v in re.findall(r"copy .*?([0-9.]+) GB/s", out)]
+        return ""
+
+
+def attainable_copy():
+    """Copy-kernel bandwidth from the calibration program (GB/s), or None."""
+    import re
+    vals = [float(v) for v in re.findall(r"copy .*?([0-9.]+) GB/s", _calibrate("copy"))]
     return max(vals) if vals else None
+
+
+def attainable_philox():
+    """Philox4x32-10 blocks/s of the library's Philox alone, from the
+    calibration program (Gblocks/s), or None."""
+    import re
+    m = re.search(r"philox attainable: ([0-9.]+) Gblocks/s", _calibrate("philox"))
+    return float(m.group(1)) if m else None
 
 
 def replica_set(n=512, seed=3):
@@ -388,6 +400,7 @@ def run(args):
     hbm_gbs = half_bytes / (half_ms * 1e-3) / 1e9
     blocks_gps = half_updates / 4.0 / (half_ms * 1e-3) / 1e9   # one 32-bit draw per update
     traffic = measured_traffic("ising_4bit") if L == 2 ** 17 else None
+    philox_alone = attainable_philox()
     res = {
         "metric": METRIC,
         "value": round(updates / (wall * 1e9), 2),
@@ -417,7 +430,9 @@ def run(args):
                      "work_per_launch": "%d Philox4x32-10 blocks (one u32 draw per update), %d bytes" % (
                          int(half_updates / 4), int(half_bytes)),
                      "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                     "valu_busy_pmc": measured_valu_busy("ising_4bit") if L == 2 ** 17 else None},
+                     "valu_busy_pmc": measured_valu_busy("ising_4bit") if L == 2 ** 17 else None,
+                     "philox_alone_Gblocks": philox_alone,
+                     "frac_of_philox_alone": round(blocks_gps / philox_alone, 4) if philox_alone else None},
         "paper_context": {"updates_per_ns": 1797, "hardware": "1x GB200, 1-bit cells with LUT random bits",
                           "note": "context only"},
         "measures": measures,

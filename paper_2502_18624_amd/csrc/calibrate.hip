@@ -4,14 +4,20 @@
 //             scale the sweep kernel's counters to bytes);
 //   read    : 4 GiB read-only stream;
 //   rrw     : read a, read b, write a (the traffic shape of a half-sweep);
-//   philox  : Philox4x32-10 blocks/s with 64-bit multiplies and with
-//             separate high/low multiplies;
+//   philox  : Philox4x32-10 blocks/s alone: the library's form (one
+//             v_mad_u64_u32 per product, one v_bitop3_b32 per pair of xors,
+//             counter words as the sweep's accept draws use them: a per-lane
+//             block index, zero high word, wave-uniform t and colour), and
+//             for comparison separate high/low multiplies with plain xors;
 //   alu/mad : 32-bit integer VALU issue rate and v_mad_u64_u32 rate.
-// Usage: mcl_calibrate [copy]   (with "copy" only the copy test runs)
+// Usage: mcl_calibrate [copy|philox]   (with an argument only that test runs)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
+
+#include "common.h"
 
 #define CHECK(x) do { hipError_t e = (x); if (e != hipSuccess) { printf("HIP error %s at %d\n", hipGetErrorString(e), __LINE__); exit(1);} } while (0)
 
@@ -39,19 +45,6 @@ __global__ void rrw_kernel(uint4* __restrict__ a, const uint4* __restrict__ b, i
     for (; i < n; i += stride) { uint4 x = a[i], y = b[i]; x.x ^= y.x; x.y ^= y.y; x.z ^= y.z; x.w ^= y.w; a[i] = x; }
 }
 
-__device__ __forceinline__ void philox_mad(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1; c3 = (uint32_t)p0; c0 = n0; c2 = n2;
-        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
-    }
-}
-
 __device__ __forceinline__ void philox_hilo(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -65,24 +58,28 @@ __device__ __forceinline__ void philox_hilo(uint32_t& c0, uint32_t& c1, uint32_t
     }
 }
 
+// Each thread generates nblk consecutive blocks, four at a time, and folds
+// their words into one output word so that nothing is optimised away.
 template <int VARIANT>
 __global__ __launch_bounds__(256) void philox_kernel(uint32_t* out, int nblk, uint32_t k0, uint32_t k1, uint32_t t)
 {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
     for (int i = 0; i < nblk; i += 4) {
-        uint32_t a0 = tid * 4096u + i, a1 = 0, a2 = t, a3 = 0;
-        uint32_t b0 = tid * 4096u + i + 1, b1 = 0, b2 = t, b3 = 0;
-        uint32_t c0 = tid * 4096u + i + 2, c1 = 0, c2 = t, c3 = 0;
-        uint32_t d0 = tid * 4096u + i + 3, d1 = 0, d2 = t, d3 = 0;
+        const uint32_t b = tid * (uint32_t)nblk + (uint32_t)i;
         if (VARIANT == 0) {
-            philox_mad(a0, a1, a2, a3, k0, k1); philox_mad(b0, b1, b2, b3, k0, k1);
-            philox_mad(c0, c1, c2, c3, k0, k1); philox_mad(d0, d1, d2, d3, k0, k1);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const mcl::Philox4 p = mcl::philox4x32_10(b + d, 0u, t, 1u, k0, k1);
+                acc += mcl::xor3(p.v0, p.v1, p.v2) ^ p.v3;
+            }
         } else {
+            uint32_t a0 = b, a1 = 0, a2 = t, a3 = 1, b0 = b + 1, b1 = 0, b2 = t, b3 = 1;
+            uint32_t c0 = b + 2, c1 = 0, c2 = t, c3 = 1, d0 = b + 3, d1 = 0, d2 = t, d3 = 1;
             philox_hilo(a0, a1, a2, a3, k0, k1); philox_hilo(b0, b1, b2, b3, k0, k1);
             philox_hilo(c0, c1, c2, c3, k0, k1); philox_hilo(d0, d1, d2, d3, k0, k1);
+            acc += (a0 ^ a1 ^ a2 ^ a3) + (b0 ^ b1 ^ b2 ^ b3) + (c0 ^ c1 ^ c2 ^ c3) + (d0 ^ d1 ^ d2 ^ d3);
         }
-        acc += (a0 ^ a1 ^ a2 ^ a3) + (b0 ^ b1 ^ b2 ^ b3) + (c0 ^ c1 ^ c2 ^ c3) + (d0 ^ d1 ^ d2 ^ d3);
     }
     out[tid] = acc;
 }
@@ -124,99 +121,101 @@ __global__ __launch_bounds__(256) void mad_kernel(uint32_t* out, int iters, uint
     out[tid] = a;
 }
 
+// Time one launch: the event pair around it, in milliseconds.
+template <typename F>
+static float timed(hipEvent_t e0, hipEvent_t e1, F launch)
+{
+    float ms = 0.f;
+    CHECK(hipEventRecord(e0));
+    launch();
+    CHECK(hipGetLastError());
+    CHECK(hipEventRecord(e1));
+    CHECK(hipEventSynchronize(e1));
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+}
+
 int main(int argc, char** argv)
 {
-    const bool copy_only = argc > 1 && argv[1][0] == 'c';
+    const bool copy_only = argc > 1 && strcmp(argv[1], "copy") == 0;
+    const bool philox_only = argc > 1 && strcmp(argv[1], "philox") == 0;
+    if (argc > 1 && !copy_only && !philox_only) {
+        fprintf(stderr, "usage: %s [copy|philox]\n", argv[0]);
+        return 2;
+    }
     hipDeviceProp_t prop;
     CHECK(hipGetDeviceProperties(&prop, 0));
     printf("device %s CUs %d clock %d kHz mem clock %d kHz bus %d LDS/CU %zu L2 %d\n", prop.gcnArchName,
            prop.multiProcessorCount, prop.clockRate, prop.memoryClockRate, prop.memoryBusWidth,
            (size_t)prop.maxSharedMemoryPerMultiProcessor, prop.l2CacheSize);
-    const int64_t bytes = (int64_t)4 << 30;   // 4 GiB per buffer
-    const int64_t n = bytes / 16;
-    uint4 *a, *b;
+    const int threads = 256 * 256 * 16;   // 1M threads
     uint32_t* out;
-    CHECK(hipMalloc(&a, bytes));
-    CHECK(hipMalloc(&b, bytes));
-    CHECK(hipMalloc(&out, (size_t)1 << 26));
-    CHECK(hipMemset(a, 1, bytes));
-    CHECK(hipMemset(b, 2, bytes));
+    CHECK(hipMalloc(&out, (size_t)threads * 4));
     hipEvent_t e0, e1;
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
-    float ms;
-    const int grid = 256 * 8 * 4;
-    for (int rep = 0; rep < 3; ++rep) {
-        CHECK(hipEventRecord(e0));
-        hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, a, b, n);
-        CHECK(hipEventRecord(e1));
-        CHECK(hipEventSynchronize(e1));
-        CHECK(hipEventElapsedTime(&ms, e0, e1));
-        printf("copy 4GiB->4GiB: %.3f ms  %.1f GB/s\n", ms, 2.0 * bytes / ms / 1e6);
-    }
-    if (copy_only) {
+    if (!philox_only) {
+        const int64_t bytes = (int64_t)4 << 30;   // 4 GiB per buffer
+        const int64_t n = bytes / 16;
+        uint4 *a, *b;
+        CHECK(hipMalloc(&a, bytes));
+        CHECK(hipMalloc(&b, bytes));
+        CHECK(hipMemset(a, 1, bytes));
+        CHECK(hipMemset(b, 2, bytes));
+        const int grid = 256 * 8 * 4;
+        for (int rep = 0; rep < 3; ++rep) {
+            const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, a, b, n); });
+            printf("copy 4GiB->4GiB: %.3f ms  %.1f GB/s\n", ms, 2.0 * bytes / ms / 1e6);
+        }
+        if (!copy_only) {
+            for (int rep = 0; rep < 3; ++rep) {
+                const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, a, n, out); });
+                printf("read 4GiB: %.3f ms  %.1f GB/s\n", ms, 1.0 * bytes / ms / 1e6);
+            }
+            for (int rep = 0; rep < 3; ++rep) {
+                const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(rrw_kernel, dim3(grid), dim3(256), 0, 0, a, b, n); });
+                printf("read a + read b + write a (4GiB each): %.3f ms  %.1f GB/s\n", ms, 3.0 * bytes / ms / 1e6);
+            }
+        }
         CHECK(hipFree(a));
         CHECK(hipFree(b));
-        CHECK(hipFree(out));
-        printf("calibrate done\n");
-        return 0;
     }
-    for (int rep = 0; rep < 3; ++rep) {
-        CHECK(hipEventRecord(e0));
-        hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, a, n, out);
-        CHECK(hipEventRecord(e1));
-        CHECK(hipEventSynchronize(e1));
-        CHECK(hipEventElapsedTime(&ms, e0, e1));
-        printf("read 4GiB: %.3f ms  %.1f GB/s\n", ms, 1.0 * bytes / ms / 1e6);
-    }
-    for (int rep = 0; rep < 3; ++rep) {
-        CHECK(hipEventRecord(e0));
-        hipLaunchKernelGGL(rrw_kernel, dim3(grid), dim3(256), 0, 0, a, b, n);
-        CHECK(hipEventRecord(e1));
-        CHECK(hipEventSynchronize(e1));
-        CHECK(hipEventElapsedTime(&ms, e0, e1));
-        printf("read a + read b + write a (4GiB each): %.3f ms  %.1f GB/s\n", ms, 3.0 * bytes / ms / 1e6);
-    }
-    // Philox: threads * nblk blocks
-    const int threads = 256 * 256 * 16;   // 1M threads; out has 16M words
-    const int nblk = 64;
-    for (int variant = 0; variant < 2; ++variant) {
-        for (int rep = 0; rep < 2; ++rep) {
-            CHECK(hipEventRecord(e0));
-            if (variant == 0)
-                hipLaunchKernelGGL(philox_kernel<0>, dim3(threads / 256), dim3(256), 0, 0, out, nblk, 1001u, 0u, 5u);
-            else
-                hipLaunchKernelGGL(philox_kernel<1>, dim3(threads / 256), dim3(256), 0, 0, out, nblk, 1001u, 0u, 5u);
-            CHECK(hipEventRecord(e1));
-            CHECK(hipEventSynchronize(e1));
-            CHECK(hipEventElapsedTime(&ms, e0, e1));
-            const double blocks = (double)threads * nblk;
-            printf("philox variant %d (%s): %.3f ms  %.3f Gblocks/s = %.1f draws/ns\n", variant,
-                   variant == 0 ? "mad_u64" : "mul_hi+mul_lo", ms, blocks / ms / 1e6, 4 * blocks / ms / 1e6);
+    if (!copy_only) {
+        // Philox: threads * nblk blocks per launch (2^30), the first launch a warm-up
+        const int nblk = 1024;
+        const double blocks = (double)threads * nblk;
+        for (int variant = 0; variant < 2; ++variant) {
+            double best = 0.0;
+            for (int rep = 0; rep < 4; ++rep) {
+                const float ms = timed(e0, e1, [&] {
+                    if (variant == 0)
+                        hipLaunchKernelGGL(philox_kernel<0>, dim3(threads / 256), dim3(256), 0, 0, out, nblk, 1001u, 0u, 5u);
+                    else
+                        hipLaunchKernelGGL(philox_kernel<1>, dim3(threads / 256), dim3(256), 0, 0, out, nblk, 1001u, 0u, 5u);
+                });
+                if (rep == 0) continue;
+                const double g = blocks / ms / 1e6;
+                if (g > best) best = g;
+                printf("philox variant %d (%s): %.3f ms  %.1f Gblocks/s = %.1f draws/ns\n", variant,
+                       variant == 0 ? "library: mad_u64 + bitop3" : "mul_hi + mul_lo, plain xors", ms, g, 4 * g);
+            }
+            if (variant == 0) printf("philox attainable: %.1f Gblocks/s\n", best);
         }
     }
-    for (int rep = 0; rep < 2; ++rep) {
-        const int iters = 256;
-        CHECK(hipEventRecord(e0));
-        hipLaunchKernelGGL(alu_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u);
-        CHECK(hipEventRecord(e1));
-        CHECK(hipEventSynchronize(e1));
-        CHECK(hipEventElapsedTime(&ms, e0, e1));
-        const double ops = (double)threads * iters * 16 * 8 * 2;
-        printf("alu xor+add: %.3f ms  %.2f Tops/s (lane ops)\n", ms, ops / ms / 1e9);
+    if (!copy_only && !philox_only) {
+        for (int rep = 0; rep < 2; ++rep) {
+            const int iters = 256;
+            const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(alu_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u); });
+            const double ops = (double)threads * iters * 16 * 8 * 2;
+            printf("alu xor+add: %.3f ms  %.2f Tops/s (lane ops)\n", ms, ops / ms / 1e9);
+        }
+        for (int rep = 0; rep < 2; ++rep) {
+            const int iters = 64;
+            const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(mad_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u); });
+            const double ops = (double)threads * iters * 16 * 8;
+            printf("mad_u64 (+1 xor each): %.3f ms  %.2f T mads/s\n", ms, ops / ms / 1e9);
+        }
     }
-    for (int rep = 0; rep < 2; ++rep) {
-        const int iters = 64;
-        CHECK(hipEventRecord(e0));
-        hipLaunchKernelGGL(mad_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u);
-        CHECK(hipEventRecord(e1));
-        CHECK(hipEventSynchronize(e1));
-        CHECK(hipEventElapsedTime(&ms, e0, e1));
-        const double ops = (double)threads * iters * 16 * 8;
-        printf("mad_u64 (+1 xor each): %.3f ms  %.2f T mads/s\n", ms, ops / ms / 1e9);
-    }
-    CHECK(hipFree(a));
-    CHECK(hipFree(b));
     CHECK(hipFree(out));
     printf("calibrate done\n");
     return 0;
