@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void lut_bucket_kernel(LutTable tab, uint2* __
 }
 
 template <bool HI0, int COLOR>
-__global__ __launch_bounds__(256) void lut_half_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
+__global__ __launch_bounds__(512) void lut_half_kernel(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
                                                        uint32_t L, uint32_t rows, uint32_t t,
                                                        const uint32_t* __restrict__ tbase, uint32_t k0, uint32_t k1,
                                                        LutTable tab, const uint2* __restrict__ buckets)
@@ -265,7 +265,10 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, const uint32_t*
     const uint2* bk = reinterpret_cast<const uint2*>(buckets);
     const int64_t rows = band_rows(g.Q, g.L);
     const int64_t threads = g.Q * (g.L / rows);
-    const dim3 grid((uint32_t)((threads + 255) / 256));
+    // 512-thread workgroups: each copies the 32 KiB bucket table into LDS
+    // once, so larger groups copy it fewer times per update (measured 0.4-3.6%
+    // faster than 256 threads at L = 2^13..2^17; 1024 threads lose occupancy)
+    const dim3 grid((uint32_t)((threads + 511) / 512));
     uint32_t* own = g.plane(color);
     const uint32_t* oth = g.plane(1 - color);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -274,17 +277,17 @@ hipError_t launch_lut_half(const Geom& g, int color, uint32_t t, const uint32_t*
     const bool hi0 = (g.L * g.L / 32) <= (int64_t(1) << 32);
     if (hi0) {
         if (color == 0)
-            hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+            hipLaunchKernelGGL((lut_half_kernel<true, 0>), grid, dim3(512), 0, s, own, oth, L, R, t, tbase, k0, k1,
                                tab, bk);
         else
-            hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+            hipLaunchKernelGGL((lut_half_kernel<true, 1>), grid, dim3(512), 0, s, own, oth, L, R, t, tbase, k0, k1,
                                tab, bk);
     } else {
         if (color == 0)
-            hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+            hipLaunchKernelGGL((lut_half_kernel<false, 0>), grid, dim3(512), 0, s, own, oth, L, R, t, tbase, k0, k1,
                                tab, bk);
         else
-            hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(256), 0, s, own, oth, L, R, t, tbase, k0, k1,
+            hipLaunchKernelGGL((lut_half_kernel<false, 1>), grid, dim3(512), 0, s, own, oth, L, R, t, tbase, k0, k1,
                                tab, bk);
     }
     return hipGetLastError();
