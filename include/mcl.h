@@ -77,7 +77,7 @@ enum {
     MCL_EMODEL = -1,    /* unknown model */
     MCL_EL = -2,        /* L not a multiple of 64, or < 64 (or PROTOCOL with L not 2^k) */
     MCL_EBETA = -3,     /* beta NaN or negative (beta = +inf is allowed) */
-    MCL_ED = -4,        /* D NaN */
+    MCL_ED = -4,        /* D NaN or infinite (Blume-Capel) */
     MCL_EINIT = -5,     /* unknown init state, or ZERO with the Ising model */
     MCL_ENOMEM = -6,    /* dev_bytes smaller than mcl_query_bytes() */
     MCL_ERANGE = -7,    /* the sweep counter t would pass 2^32 - 1; bad window */
@@ -122,7 +122,7 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
 
 /* n checkerboard sweeps (section 3.1: colour 0, then colour 1)
  * of single-spin Metropolis updates (section 1) at inverse temperature beta
- * and crystal field D (ignored for Ising).  Ising: a spin with 3 aligned
+ * and crystal field D (finite; ignored for Ising).  Ising: a spin with 3 aligned
  * neighbours flips with probability e^{-4 beta}, with 4 with e^{-8 beta},
  * otherwise always (section 3.2).  Blume-Capel: the proposal is one of the
  * two other values, chosen by the proposal bit (0: next value cyclically in
@@ -160,7 +160,9 @@ int mcl_rset(int corr_mode, int64_t L, int64_t t, int32_t* r, int32_t cap, int32
 /* The acceptance thresholds sweep() uses.  Ising: thr[0] = floor(2^32
  * e^{-4 beta}), thr[1] = floor(2^32 e^{-8 beta}), always[] unused.
  * Blume-Capel: 54 entries indexed ((s+1)*2 + b)*9 + (h+4); always[i] = 1
- * where dE <= 0.  dE = -h (s' - s) + D (s'^2 - s^2) in double, that order. */
+ * where dE <= 0.  dE = -h (s' - s) + D (s'^2 - s^2) in double, that order.
+ * Errors: MCL_EMODEL, MCL_EBETA, MCL_ED (Blume-Capel with D NaN or
+ * infinite), MCL_EARG, MCL_EBUFSZ (cap < 2, or < 54 for Blume-Capel). */
 int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* always, int32_t cap);
 
 /* Table of MCL_ISING_LUT (section 3.2): with p = exp(-4 beta) and each of

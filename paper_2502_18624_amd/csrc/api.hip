@@ -193,7 +193,9 @@ std::vector<int32_t> distances(int mode, int64_t L, int64_t t, int32_t* n_all)
 int check_params(const mcl_lattice* h, double beta, double D)
 {
     if (std::isnan(beta) || beta < 0.0) return MCL_EBETA;
-    if (h->model == MCL_BC && std::isnan(D)) return MCL_ED;
+    // an infinite D would make dE = D (s'^2 - s^2) undefined (infinity times
+    // zero) for the moves s -> -s
+    if (h->model == MCL_BC && !std::isfinite(D)) return MCL_ED;
     return MCL_OK;
 }
 
@@ -550,7 +552,7 @@ const char* mcl_strerror(int code)
     case MCL_EMODEL: return "unknown model";
     case MCL_EL: return "L must be a multiple of 64 in [64, 2^20] (a power of two for the protocol)";
     case MCL_EBETA: return "beta must be >= 0 (NaN rejected)";
-    case MCL_ED: return "D must not be NaN";
+    case MCL_ED: return "D must be finite";
     case MCL_EINIT: return "unknown initial state for this model";
     case MCL_ENOMEM: return "device buffer smaller than mcl_query_bytes()";
     case MCL_ERANGE: return "value out of range (sweep counter or window)";
@@ -591,7 +593,7 @@ int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* alw
         ising_thresholds(beta, thr[0], thr[1]);
         return MCL_OK;
     }
-    if (std::isnan(D)) return MCL_ED;
+    if (!std::isfinite(D)) return MCL_ED;
     if (cap < 54 || !always) return cap < 54 ? MCL_EBUFSZ : MCL_EARG;
     mcl::BCTable tb;
     bc_table(beta, D, tb);

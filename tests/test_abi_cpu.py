@@ -132,8 +132,8 @@ def test_argument_errors_before_device_work(mcl):
     assert lib.mcl_rset(2, 96 * 2, 0, None, 0, None) == -2                               # protocol needs 2^k
     assert lib.mcl_thresholds(0, float("nan"), 0.0, (ctypes.c_uint32 * 54)(), None, 54) == -3
     assert lib.mcl_thresholds(0, -1.0, 0.0, (ctypes.c_uint32 * 54)(), None, 54) == -3
-    assert lib.mcl_thresholds(1, 0.5, float("nan"), (ctypes.c_uint32 * 54)(),
-                              (ctypes.c_uint8 * 54)(), 54) == -4
+    for D in (float("nan"), float("inf"), -float("inf")):                               # MCL_ED
+        assert lib.mcl_thresholds(1, 0.5, D, (ctypes.c_uint32 * 54)(), (ctypes.c_uint8 * 54)(), 54) == -4
     for code in range(0, -12, -1):
         assert lib.mcl_strerror(code)
 
