@@ -199,8 +199,10 @@ int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, i
  * models, sizes, beta and D) by n[i] sweeps each.  Replicas advance sweep by
  * sweep together: one launch per model and colour covers every replica
  * (each workgroup belongs to one replica, so its parameters are
- * wave-uniform).  All lattices must use the stream of hs[0] (MCL_EARG
- * otherwise).  Every lattice ends bit-identical to n[i] sweep() calls on it
+ * wave-uniform).  All lattices must use the stream of hs[0], and no two
+ * entries with n[i] > 0 may share device memory (the same handle twice, or
+ * handles on overlapping buffers), which would race: MCL_EARG otherwise,
+ * before anything is queued.  Every lattice ends bit-identical to n[i] sweep() calls on it
  * alone, whatever the tuning.  1-bit lattices (MCL_ISING_LUT) advance
  * through sweep() within the call.  MCL_ERANGE if the replicas of one model
  * need more than 2^24 workgroups (2^32 work-items) in one launch.  The

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/mcl.h"
@@ -885,6 +886,17 @@ int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const doubl
         if (pc) return pc;
         if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
     }
+    // entries that do work must not share device memory: their updates would
+    // run concurrently on the same cells
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int i = 0; i < count; ++i)
+        if (n[i] > 0) {
+            const uintptr_t a = (uintptr_t)hs[i]->g.plane0;
+            spans.emplace_back(a, a + (uintptr_t)(2 * hs[i]->g.plane_words() * 4));
+        }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return MCL_EARG;
     // 1-bit replicas are advanced one lattice per launch after the batched
     // launches of the 4-bit replicas (they are independent lattices)
     std::vector<int64_t> n4(n, n + count);

@@ -211,6 +211,27 @@ def test_group_sweep_rejects_mixed_streams(mcl):
         mcl.group_sweep([a, b], [1, 1], [0.5, 0.5])
 
 
+def test_group_sweep_rejects_shared_memory(mcl):
+    """The same handle twice, or two handles on one device buffer, both
+    with work in one call: rejected before anything is queued.  An entry
+    with no work may share memory with another."""
+    print("group shared memory", flush=True)
+    L, beta = 128, BETA_C
+    a = mcl.Lattice(0, L, 31)
+    before = a.read()
+    with pytest.raises(mcl.MclError):
+        mcl.group_sweep([a, a], [2, 1], [beta, beta])
+    assert a.t == 0 and np.array_equal(a.read(), before)
+    b = mcl.Lattice(0, L, 32, mem=a.mem)                # b's initial state now fills the buffer
+    with pytest.raises(mcl.MclError):
+        mcl.group_sweep([a, b], [1, 1], [beta, beta])
+    assert a.t == 0 and b.t == 0
+    mcl.group_sweep([a, b], [2, 0], [beta, beta])
+    assert a.t == 2 and b.t == 0
+    want = _oracle_run(0, L, 31, 0, 2, beta, 0.0, start=oracle.init(0, L, 32))
+    assert np.array_equal(a.read(), want)
+
+
 def test_group_sweep_equals_plain(mcl):
     rng = np.random.default_rng(3)
     specs = []
