@@ -93,6 +93,20 @@ def measured_traffic(name):
     return None if k is None else round(k["hbm_bytes_per_launch"])
 
 
+def traffic_source():
+    """Where roofline.traffic comes from, and whether it applies to the
+    kernel source being timed."""
+    path = os.path.join(ROOT, "profiles", "traffic_sweep_kernels.json")
+    try:
+        with open(path) as f:
+            sha = json.load(f).get("kernel_source_sha")
+    except (OSError, ValueError):
+        return "no PMC summary found (profiles/traffic_sweep_kernels.json)"
+    state = "current" if sha == kernel_source_sha() else "stale: kernel source changed since, traffic null"
+    return "rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE (profiles/traffic_sweep_kernels.md), kernel source %s: %s" % (
+        sha, state)
+
+
 def measured_valu_busy(name):
     """Fraction of SIMD cycles issuing VALU instructions (PMC), or None."""
     k = profile_record(name)
@@ -426,6 +440,7 @@ def run(args):
         "roofline": {"bound": "alu", "achieved": round(blocks_gps, 1), "peak": round(PHILOX_PEAK_GBLOCKS, 1),
                      "unit": "Gblocks/s", "frac": round(blocks_gps / PHILOX_PEAK_GBLOCKS, 4),
                      "traffic": traffic,
+                     "traffic_source": traffic_source(),
                      "kernel": "half_sweep_kernel<Ising>", "avg_launch_ms": round(half_ms, 4),
                      "work_per_launch": "%d Philox4x32-10 blocks (one u32 draw per update), %d bytes" % (
                          int(half_updates / 4), int(half_bytes)),
