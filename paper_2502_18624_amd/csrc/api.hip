@@ -551,7 +551,7 @@ const char* mcl_strerror(int code)
     switch (code) {
     case MCL_OK: return "ok";
     case MCL_EMODEL: return "unknown model";
-    case MCL_EL: return "L must be a multiple of 64 in [64, 2^20] (a power of two for the protocol)";
+    case MCL_EL: return "L must be a multiple of 64 (256 for 1-bit cells), at most 2^20 (a power of two for the protocol)";
     case MCL_EBETA: return "beta must be >= 0 (NaN rejected)";
     case MCL_ED: return "D must be finite";
     case MCL_EINIT: return "unknown initial state for this model";
