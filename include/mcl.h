@@ -75,7 +75,7 @@ enum { MCL_CORR_NONE = 0, MCL_CORR_FULL = 1, MCL_CORR_PROTOCOL = 2 };
 enum {
     MCL_OK = 0,
     MCL_EMODEL = -1,    /* unknown model */
-    MCL_EL = -2,        /* L not a multiple of 64, or < 64 (or PROTOCOL with L not 2^k) */
+    MCL_EL = -2,        /* L not a multiple of 64 (256 for MCL_ISING_LUT), < 64 or > 2^20 (or PROTOCOL with L not 2^k) */
     MCL_EBETA = -3,     /* beta NaN or negative (beta = +inf is allowed) */
     MCL_ED = -4,        /* D NaN or infinite (Blume-Capel) */
     MCL_EINIT = -5,     /* unknown init state, or ZERO with the Ising model */
