@@ -426,7 +426,8 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u4 cells, u32 Philox draws (integer path)",
+        "dtype": "u32",
+        "arithmetic": "integer only: 4-bit cells packed in u32 words, u32 Philox4x32-10 draws, u32 thresholds",
         "data": "synthetic (seeded Philox4x32-10 random start)",
         "config": {"workload": "Ising quench, L=2^17, T=T_c, random +-1 start, %d sweeps, protocol C(r,t) and "
                                "B/M at %s, one lattice per launch" % (
