@@ -180,7 +180,8 @@ double ora_ising_flip_prob(int aligned, double beta)
     return 1.0;
 }
 
-/* Blume-Capel proposal (the paper only says "Metropolis", section 1):
+/* Blume-Capel proposal (the paper names Metropolis updates, section 1, but
+ * no proposal rule):
  * reading -- propose one of the two other values of {-1,0,+1} uniformly,
  * b = 0 picks the next value cyclically, b = 1 the one after. */
 static int bc_propose(int s, int b)

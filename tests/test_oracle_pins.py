@@ -335,6 +335,71 @@ def test_zero_temperature_is_monotone(model, D):
         e_prev = e
 
 
+def _aligned(s, x, y):
+    L = s.shape[0]
+    v = s[y, x]
+    return sum(int(n == v) for n in (s[y, (x + 1) % L], s[y, (x - 1) % L], s[(y + 1) % L, x], s[(y - 1) % L, x]))
+
+
+@pytest.mark.parametrize("model", [oracle.ISING, oracle.ISING_LUT])
+def test_zero_temperature_limit_is_the_majority_rule(model):
+    """At beta = infinity the Metropolis rule of section 3.2 needs no random
+    numbers: e^{-4 beta} = e^{-8 beta} = 0, so a spin flips iff dE <= 0, i.e.
+    iff at most two of its four neighbours are aligned (ties flip).  One sweep
+    equals that deterministic rule applied to colour 0, then to colour 1."""
+    for seed in (1, 2, 3):
+        L = 10
+        s = oracle.init(model, L, seed)
+        ref = s.copy()
+        oracle.sweep(s, model, seed, 0, 1, float("inf"))
+        for c in (0, 1):
+            flips = [(x, y) for y in range(L) for x in range(L) if (x + y) % 2 == c and _aligned(ref, x, y) <= 2]
+            for x, y in flips:
+                ref[y, x] = -ref[y, x]
+        assert np.array_equal(s, ref), (model, seed)
+
+
+@pytest.mark.parametrize("model", [oracle.ISING, oracle.ISING_LUT])
+def test_infinite_temperature_flips_every_spin(model):
+    """At beta = 0 every Ising move is accepted (4-bit: u < 2^32 - 1, which
+    these seeds never miss; 1-bit: p = 1 sets every pattern bit), so each
+    sweep maps s to -s."""
+    s = oracle.init(model, 16, 9)
+    s0 = s.copy()
+    oracle.sweep(s, model, 9, 0, 1, 0.0)
+    assert np.array_equal(s, -s0)
+    oracle.sweep(s, model, 9, 1, 1, 0.0)
+    assert np.array_equal(s, s0)
+
+
+def test_sweep_uses_the_contract_draws():
+    """The counter plumbing of a sweep: after sweep t from s0, every colour-0
+    site (updated first, from colour-1 neighbours still as in s0) has flipped
+    exactly as the section 3.2 rule says for its accept draw u(seed, t, 0, k),
+    k = (y L + x) >> 1 -- the draw whose values the rocRAND pin fixes.  At
+    e^{-4 beta} = 1/2 about half the draw-dependent sites flip."""
+    beta = math.log(2.0) / 4.0
+    T4, T8 = oracle.ising_thresholds(beta)
+    L, seed, checked = 16, 77, 0
+    for t in (0, 5, 123456):
+        s0 = oracle.init(oracle.ISING, L, seed + t)
+        s = s0.copy()
+        oracle.sweep(s, oracle.ISING, seed, t, 1, beta)
+        for y in range(L):
+            for x in range(L):
+                if (x + y) % 2:
+                    continue
+                a = _aligned(s0, x, y)
+                if a <= 2:
+                    want = True
+                else:
+                    u = oracle.accept_draw(seed, t, 0, (y * L + x) >> 1)
+                    want = u < (T4 if a == 3 else T8)
+                    checked += 1
+                assert (s[y, x] == -s0[y, x]) == want, (t, x, y)
+    assert checked > 50
+
+
 def test_ising_global_flip_symmetry():
     """Acceptance depends only on the aligned count, so the trajectory from
     -s0 is exactly minus the trajectory from s0."""
