@@ -83,6 +83,12 @@ MUTANTS = [
     # d equal to r_c is already the last distance of the linear part)
     ("log-spaced set from 2R", "if (d > rc && d <= half)", "if (d > 2 * CORR_R && d <= half)"),
     ("sigma h histogram sign", "hist[v * h + 4]++;", "hist[-v * h + 4]++;"),
+    # the light-cone window (what the full-size GPU tests compare against)
+    ("window ising always-flip bound", "int flip = aligned <= 2;\n                        if (!flip) flip = ora_accept",
+     "int flip = aligned <= 1;\n                        if (!flip) flip = ora_accept"),
+    ("window neighbour repeated", "nb[3] = patch[(j - 1) * P + i];", "nb[3] = patch[(j + 1) * P + i];"),
+    ("window lut exp8 without exp4", "if (aligned == 4 && e4)", "if (aligned == 4)"),
+    ("window bc table index", "< tb.thr[sv + 1][b][h + 4];", "< tb.thr[sv + 1][1 - b][h + 4];"),
 ]
 
 # pins ordered by cost, so that most mutants stop early: the enumerations
