@@ -20,7 +20,7 @@ from ._lib import BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_RANDOM, ISING, I
 from .lattice import Lattice, correlation, energy, schwinger_dyson
 from .schedule import paper_times, pow2_times
 
-MODELS = {"ising": ISING, "blume-capel": BC, "ising-1bit": ISING_LUT}
+MODELS = {"ising": ISING, "blume-capel": BC, "bc": BC, "ising-1bit": ISING_LUT}
 CORR = {"none": CORR_NONE, "full": CORR_FULL, "protocol": CORR_PROTOCOL}
 
 
