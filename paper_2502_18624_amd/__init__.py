@@ -8,5 +8,5 @@ supplies device memory and streams through PyTorch.
 """
 from ._lib import (BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_DOWN, INIT_RANDOM,  # noqa: F401
                    INIT_UP, INIT_ZERO, ISING, ISING_LUT, MclError, lib)
-from .lattice import (Lattice, correlation, energy, group_sweep, lut_table, query_bytes, rset,  # noqa: F401
-                      schwinger_dyson, thresholds)
+from .lattice import (Lattice, correlation, correlation_length, energy, group_sweep, lut_table, query_bytes,  # noqa: F401
+                      rset, schwinger_dyson, thresholds)

@@ -75,6 +75,36 @@ def correlation(m: dict):
     return np.asarray(m["Cx"]) / ns, np.asarray(m["Cy"]) / ns
 
 
+def correlation_length(r, C, k: int = 1) -> float:
+    """Integral estimator xi_{k,k+1} = I_{k+1} / I_k of the correlation
+    length xi(t), the growing domain size of a quench (section 1; the paper
+    takes its estimators from a cited reference).  I_k is the integral of
+    r^k C(r) dr over the measured distances r (ascending; the protocol's
+    log-spaced tail included), by the trapezoid rule on that grid, up to the
+    last distance before C first drops to zero or below (where noise takes
+    over).  C is a normalised correlation, e.g. the mean of the two axes of
+    correlation(m).  For C(r) = exp(-r/a), xi_{1,2} = 2a and xi_{2,3} = 3a."""
+    r = np.asarray(r, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    if r.ndim != 1 or r.shape != C.shape or r.size < 2:
+        raise ValueError("r and C must be 1-d arrays of the same length, at least 2")
+    if np.any(np.diff(r) <= 0) or r[0] < 0:
+        raise ValueError("r must be non-negative and strictly increasing")
+    if k < 0:
+        raise ValueError("k must be >= 0")
+    nonpos = np.nonzero(C <= 0.0)[0]
+    n = int(nonpos[0]) if nonpos.size else r.size
+    if n < 2:
+        raise ValueError("C must stay positive over at least two distances")
+    r, C = r[:n], C[:n]
+
+    def integral(p):
+        f = r ** p * C
+        return float(np.sum(0.5 * (f[1:] + f[:-1]) * np.diff(r)))
+
+    return integral(k + 1) / integral(k)
+
+
 class Lattice:
     """One L x L lattice resident in HBM (two 4-bit colour planes)."""
 

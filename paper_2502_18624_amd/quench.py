@@ -17,7 +17,7 @@ import sys
 import numpy as np
 
 from ._lib import BC, CORR_FULL, CORR_NONE, CORR_PROTOCOL, INIT_RANDOM, ISING, ISING_LUT
-from .lattice import Lattice, correlation, energy, schwinger_dyson
+from .lattice import Lattice, correlation, correlation_length, energy, schwinger_dyson
 from .schedule import paper_times, pow2_times
 
 MODELS = {"ising": ISING, "blume-capel": BC, "bc": BC, "ising-1bit": ISING_LUT}
@@ -28,7 +28,11 @@ def run_quench(model, L, seed, beta, D=0.0, sweeps=1024, schedule="pow2", corr=C
                device="cuda", stream=None):
     """Yield one measurement dict per time of the schedule (t <= sweeps):
     the integer sums of measure(), plus "E", "schwinger_dyson" and, with a
-    correlation mode, the normalised "Cx_norm" and "Cy_norm"."""
+    correlation mode, the normalised "Cx_norm" and "Cy_norm", the integral
+    estimators "xi12" and "xi23" of the correlation length from their mean
+    (None while it is not positive at r = 1), and "L_over_xi12", which
+    section 1 wants to stay above about 50 for results free of finite-size
+    effects."""
     times = paper_times(sweeps) if schedule == "paper" else pow2_times(sweeps)
     lat = Lattice(model, L, seed, init, device=device, stream=stream)
     try:
@@ -39,6 +43,11 @@ def run_quench(model, L, seed, beta, D=0.0, sweeps=1024, schedule="pow2", corr=C
             m["schwinger_dyson"] = schwinger_dyson(m["sd"], beta) if math.isfinite(beta) else None
             if corr != CORR_NONE:
                 m["Cx_norm"], m["Cy_norm"] = correlation(m)
+                c = 0.5 * (m["Cx_norm"] + m["Cy_norm"])
+                ok = c.size > 1 and c[1] > 0
+                m["xi12"] = correlation_length(m["r"], c, 1) if ok else None
+                m["xi23"] = correlation_length(m["r"], c, 2) if ok else None
+                m["L_over_xi12"] = L / m["xi12"] if m["xi12"] else None
             yield m
     finally:
         lat.free()

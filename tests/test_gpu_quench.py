@@ -45,6 +45,22 @@ def test_run_quench_equals_oracle(mcl, model, D, schedule):
         assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy)
         assert np.allclose(m["Cx_norm"], Cx / ns) and m["Cx_norm"][0] == m["Q"] / L**2     # C(0) = Q / N
         assert m["schwinger_dyson"] == mcl.schwinger_dyson(oracle.sd_hist(s), beta)
+        c = 0.5 * (Cx / ns + Cy / ns)                      # as run_quench forms it
+        assert m["xi12"] == mcl.correlation_length(m["r"], c, 1)
+
+
+def test_correlation_length_grows_in_a_critical_quench(mcl):
+    """Ising at T_c from a random start, L = 2048: the domain size xi_{1,2}
+    grows with t (slightly slower than sqrt(t), section 3.3), and L / xi
+    stays far above the 50 that section 1 asks for."""
+    from paper_2502_18624_amd.quench import run_quench
+    got = [m for m in run_quench(0, 2048, 7, BETA_C, 0.0, 256) if m["t"] >= 4]
+    xi = np.array([m["xi12"] for m in got])
+    t = np.array([m["t"] for m in got], dtype=float)
+    assert np.all(np.diff(xi) > 0), xi
+    growth = np.log(xi[-1] / xi[0]) / np.log(t[-1] / t[0])          # effective exponent
+    assert 0.25 < growth < 0.6, growth
+    assert all(m["L_over_xi12"] > 50 for m in got)
 
 
 def test_quench_command_line(mcl, tmp_path):
