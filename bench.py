@@ -398,10 +398,14 @@ def run(args):
             tm = time.perf_counter()
             out = lat.measure(mcl.CORR_PROTOCOL)
             t_meas += time.perf_counter() - tm
+            cx, cy = mcl.correlation(out)
+            c = 0.5 * (cx + cy)
+            xi = mcl.correlation_length(out["r"], c, 1) if c[1] > 0 else None
             measures.append({"t": out["t"], "B": out["B"], "M": out["M"], "n_r": int(len(out["r"])),
                              "Cx1": int(out["Cx"][1]), "Cy1": int(out["Cy"][1]),
-                             "schwinger_dyson": round(mcl.schwinger_dyson(out["sd"], beta), 7)})
-            log("  t=%d B=%d M=%d" % (out["t"], out["B"], out["M"]))
+                             "schwinger_dyson": round(mcl.schwinger_dyson(out["sd"], beta), 7),
+                             "xi12": round(xi, 3) if xi else None})
+            log("  t=%d B=%d M=%d xi12=%s" % (out["t"], out["B"], out["M"], "%.2f" % xi if xi else "-"))
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     sweep_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
