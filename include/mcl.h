@@ -153,8 +153,10 @@ int sweep(mcl_lattice* h, int64_t n, double beta, double D);
  * changes the launch shape only, never the result. */
 int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out);
 
-/* Distances measure() would use for (mode, L, t); returns their number or
- * MCL_EBUFSZ (with *n_needed set) if cap is too small. */
+/* Distances measure() would use for (mode, L, t); returns their number, or
+ * MCL_EBUFSZ (with *n_needed set) if cap is too small or r is NULL;
+ * MCL_EARG for an unknown mode, L < 2 or t < 0; MCL_EL for the protocol
+ * with L not a power of two. */
 int mcl_rset(int corr_mode, int64_t L, int64_t t, int32_t* r, int32_t cap, int32_t* n_needed);
 
 /* The acceptance thresholds sweep() uses.  Ising: thr[0] = floor(2^32
@@ -173,26 +175,31 @@ int mcl_thresholds(int model, double beta, double D, uint32_t* thr, uint8_t* alw
  * group g.  Two streams per group g (e = 0: exp4, e = 1: ANDed with exp4
  * into exp8): ctr = (g>>2 lo, g>>2 hi, t, 8 + 2c + e), output word g & 3.
  * A site flips always with at most 2 aligned neighbours, iff its exp4 bit
- * with 3, iff its exp8 bit with 4. */
+ * with 3, iff its exp8 bit with 4.  Errors: MCL_EBETA, MCL_EARG (T16 NULL). */
 int mcl_lut_table(double beta, uint64_t* T16);
 
 /* Copy the lattice to host memory as L*L int8 spins, row-major [y][x].
- * Synchronous.  Used for parity checks and checkpoints. */
+ * Synchronous.  Used for parity checks and checkpoints.  MCL_EARG on NULL. */
 int lattice_read(mcl_lattice* h, int8_t* host_spins);
 
-/* Window [x0, x0+w) x [y0, y0+hgt) (periodic) as w*hgt int8 spins. */
+/* Window [x0, x0+w) x [y0, y0+hgt) (periodic) as w*hgt int8 spins, row-major.
+ * Synchronous.  MCL_ERANGE unless 0 <= x0, y0 < L and 1 <= w, hgt <= L. */
 int lattice_read_window(mcl_lattice* h, int64_t x0, int64_t y0, int64_t w, int64_t hgt,
                         int8_t* host_spins);
 
-/* Raw colour planes (both, plane 0 first, mcl_query_bytes layout);
- * bytes must be >= L*L/2.  For checkpoints of large lattices. */
+/* Raw colour planes (both, plane 0 first, in the device layout): L*L/2
+ * bytes for 4-bit cells, L*L/8 for 1-bit cells; MCL_EBUFSZ if bytes is
+ * smaller.  For checkpoints of large lattices.  The write takes the cells
+ * as they are (a cell that holds no spin value is counted by measure() as
+ * invalid) and sets the sweep counter t (MCL_ERANGE unless 0 <= t <= 2^32). */
 int lattice_read_packed(mcl_lattice* h, void* host, int64_t bytes);
 int lattice_write_packed(mcl_lattice* h, const void* host, int64_t bytes, int64_t t);
 
-/* Restore: L*L int8 spins (valid for the model) and the sweep counter t. */
+/* Restore: L*L int8 spins and the sweep counter t.  MCL_ESPINS for a value
+ * the model does not have (0 for Ising), MCL_ERANGE unless 0 <= t <= 2^32. */
 int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t);
 
-/* Handle state. */
+/* Handle state; NULL outputs are skipped.  MCL_EARG if h is NULL. */
 int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, int64_t* t);
 
 /* Batched path: advance `count` independent lattices (any mix of
@@ -202,8 +209,8 @@ int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, i
  * wave-uniform).  All lattices must use the stream of hs[0], and no two
  * entries with n[i] > 0 may share device memory (the same handle twice, or
  * handles on overlapping buffers), which would race: MCL_EARG otherwise,
- * before anything is queued.  Every lattice ends bit-identical to n[i] sweep() calls on it
- * alone, whatever the tuning.  1-bit lattices (MCL_ISING_LUT) advance
+ * before anything is queued.  Every lattice ends bit-identical to n[i]
+ * sweep() calls on it alone, whatever the tuning.  1-bit lattices (MCL_ISING_LUT) advance
  * through sweep() within the call.  MCL_ERANGE if the replicas of one model
  * need more than 2^24 workgroups (2^32 work-items) in one launch.  The
  * library keeps a few small workspaces of its own (descriptors, pinned
