@@ -15,8 +15,8 @@
  *    Ising model (eq. IM) E = -B.
  *  - The lattice is L x L, periodic, site (x, y) with x the fast axis; its
  *    colour is (x + y) & 1 (checkerboard decomposition, section 3.1) and a
- *    sweep updates colour 0, then colour 1.  L must be a multiple of 64 and
- *    at least 64.
+ *    sweep updates colour 0, then colour 1.  L must be a multiple of 64
+ *    (of 256 for MCL_ISING_LUT), at least 64 and at most 2^20.
  *  - Randomness is counter-based Philox4x32-10 keyed by the 64-bit seed and
  *    addressed by (sweep t, colour, logical site), so results do not depend
  *    on storage layout, batching or launch shape: every lattice is
