@@ -71,7 +71,7 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 P(i64), P(i64)]
         L.ora_sweep.restype = ctypes.c_int
-        L.ora_measure.argtypes = [ctypes.c_void_p, i64, P(i64), P(i64), P(i64), P(i64)]
+        L.ora_measure.argtypes = [ctypes.c_void_p, i64, P(i64), P(i64), P(i64), P(i64), ctypes.c_int]
         L.ora_rset.argtypes = [ctypes.c_int, i64, i64, P(i32), ctypes.c_int]
         L.ora_rset.restype = ctypes.c_int
         L.ora_rc.argtypes = [i64, i64]
@@ -79,8 +79,8 @@ def lib():
         L.ora_g.argtypes = [i64]
         L.ora_g.restype = ctypes.c_double
         L.ora_corr.argtypes = [ctypes.c_void_p, i64, ctypes.c_int, P(i32), ctypes.c_int,
-                               P(i64), P(i64), P(i64)]
-        L.ora_sd_hist.argtypes = [ctypes.c_void_p, i64, P(i64)]
+                               P(i64), P(i64), P(i64), ctypes.c_int]
+        L.ora_sd_hist.argtypes = [ctypes.c_void_p, i64, P(i64), ctypes.c_int]
         L.ora_init_window.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_int, i64, u64, ctypes.c_int]
         L.ora_init_window.restype = ctypes.c_int
         L.ora_sweep_window.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_int, i64, u64, i64, i64,
@@ -190,11 +190,11 @@ def sweep(s, model, seed, t0, n, beta, D=0.0, nthreads=1, track=False):
     return None
 
 
-def measure(s):
+def measure(s, nthreads=1):
     L = s.shape[0]
     B, M, Q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     cnt = (ctypes.c_int64 * 3)()
-    lib().ora_measure(s.ctypes.data, L, ctypes.byref(B), ctypes.byref(M), ctypes.byref(Q), cnt)
+    lib().ora_measure(s.ctypes.data, L, ctypes.byref(B), ctypes.byref(M), ctypes.byref(Q), cnt, int(nthreads))
     return {"B": B.value, "M": M.value, "Q": Q.value, "counts": [int(c) for c in cnt]}
 
 
@@ -216,7 +216,7 @@ def rset(mode, L, t=0):
         cap = -n
 
 
-def corr(s, mode, r):
+def corr(s, mode, r, nthreads=1):
     L = s.shape[0]
     r = np.ascontiguousarray(r, dtype=np.int32)
     nr = len(r)
@@ -224,13 +224,13 @@ def corr(s, mode, r):
     Cy = np.zeros(nr, dtype=np.int64)
     ns = np.zeros(nr, dtype=np.int64)
     lib().ora_corr(s.ctypes.data, L, mode, _ptr(r, ctypes.c_int32), nr,
-                   _ptr(Cx, ctypes.c_int64), _ptr(Cy, ctypes.c_int64), _ptr(ns, ctypes.c_int64))
+                   _ptr(Cx, ctypes.c_int64), _ptr(Cy, ctypes.c_int64), _ptr(ns, ctypes.c_int64), int(nthreads))
     return Cx, Cy, ns
 
 
-def sd_hist(s):
+def sd_hist(s, nthreads=1):
     h = np.zeros(9, dtype=np.int64)
-    lib().ora_sd_hist(s.ctypes.data, s.shape[0], _ptr(h, ctypes.c_int64))
+    lib().ora_sd_hist(s.ctypes.data, s.shape[0], _ptr(h, ctypes.c_int64), int(nthreads))
     return h
 
 

@@ -243,8 +243,11 @@ int ora_init(int8_t* s, int model, int64_t L, uint64_t seed, int init_state)
 /* ------------------------------------------------------------------------ */
 static int8_t at(const int8_t* s, int64_t L, int64_t x, int64_t y)
 {
-    x = ((x % L) + L) % L;
-    y = ((y % L) + L) % L;
+    /* periodic boundaries; coordinates already inside skip the divisions */
+    if (x < 0 || x >= L)
+        x = ((x % L) + L) % L;
+    if (y < 0 || y >= L)
+        y = ((y % L) + L) % L;
     return s[y * L + x];
 }
 
@@ -415,10 +418,17 @@ int ora_sweep(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0,
 /* E = -B + D Q), M, Q and the number of spins of each value.                */
 /* ------------------------------------------------------------------------ */
 void ora_measure(const int8_t* s, int64_t L, int64_t* B, int64_t* M, int64_t* Q,
-                 int64_t counts[3])
+                 int64_t counts[3], int nthreads)
 {
-    int64_t x, y, b = 0, m = 0, q = 0, c0 = 0, c1 = 0, c2 = 0;
-    for (y = 0; y < L; y++)
+    int64_t y, b = 0, m = 0, q = 0, c0 = 0, c1 = 0, c2 = 0;
+    if (nthreads < 1) nthreads = 1;
+    /* plain sums; with nthreads > 1 the rows are split over OpenMP threads
+     * (integer sums, so the result does not depend on the split) */
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) reduction(+ : b, m, q, c0, c1, c2) schedule(static)
+#endif
+    for (y = 0; y < L; y++) {
+        int64_t x;
         for (x = 0; x < L; x++) {
             int v = s[y * L + x];
             b += v * (at(s, L, x + 1, y) + at(s, L, x, y + 1));
@@ -428,6 +438,7 @@ void ora_measure(const int8_t* s, int64_t L, int64_t* B, int64_t* M, int64_t* Q,
             else if (v == 0) c1++;
             else if (v == 1) c2++;
         }
+    }
     *B = b; *M = m; *Q = q;
     counts[0] = c0; counts[1] = c1; counts[2] = c2;
 }
@@ -490,21 +501,29 @@ int ora_rset(int mode, int64_t L, int64_t t, int32_t* r, int cap)
 }
 
 void ora_corr(const int8_t* s, int64_t L, int mode, const int32_t* r, int nr,
-              int64_t* Cx, int64_t* Cy, int64_t* nsrc)
+              int64_t* Cx, int64_t* Cy, int64_t* nsrc, int nthreads)
 {
     int j;
+    if (nthreads < 1) nthreads = 1;
     for (j = 0; j < nr; j++) {
-        int64_t d = r[j], x, y, sx = 0, sy = 0, cnt = 0;
+        int64_t d = r[j], y, sx = 0, sy = 0, cnt = 0;
         int sampled = (mode == ORA_CORR_PROTOCOL) && d > 2 * CORR_R;
-        for (y = 0; y < L; y++)
+        /* rows split over OpenMP threads when nthreads > 1 (integer sums) */
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) reduction(+ : sx, sy, cnt) schedule(static)
+#endif
+        for (y = 0; y < L; y++) {
+            int64_t x;
+            if (sampled && (y % CORR_R) != 0) continue;         /* source rows y = 0 (mod R) */
             for (x = 0; x < L; x++) {
                 int v;
-                if (sampled && ((x % CORR_R) != 0 || (y % CORR_R) != 0)) continue;
+                if (sampled && (x % CORR_R) != 0) continue;     /* source columns x = 0 (mod R) */
                 v = s[y * L + x];
                 sx += v * at(s, L, x + d, y);
                 sy += v * at(s, L, x, y + d);
                 cnt++;
             }
+        }
         Cx[j] = sx; Cy[j] = sy; nsrc[j] = cnt;
     }
 }
@@ -512,17 +531,26 @@ void ora_corr(const int8_t* s, int64_t L, int mode, const int32_t* r, int nr,
 /* Schwinger-Dyson identity (eq. SDI): the sum of exp(-2 beta sigma h) takes
  * as many distinct values as sigma*h does, so a histogram of sigma*h over
  * the lattice is all a device needs to count. */
-void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9])
+void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9], int nthreads)
 {
-    int64_t x, y;
-    int k;
-    for (k = 0; k < 9; k++) hist[k] = 0;
-    for (y = 0; y < L; y++)
+    int64_t y, h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0, h6 = 0, h7 = 0, h8 = 0;
+    if (nthreads < 1) nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) reduction(+ : h0, h1, h2, h3, h4, h5, h6, h7, h8) schedule(static)
+#endif
+    for (y = 0; y < L; y++) {
+        int64_t x;
+        int64_t row[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (x = 0; x < L; x++) {
             int v = s[y * L + x];
             int h = at(s, L, x + 1, y) + at(s, L, x - 1, y) + at(s, L, x, y + 1) + at(s, L, x, y - 1);
-            hist[v * h + 4]++;
+            row[v * h + 4]++;
         }
+        h0 += row[0]; h1 += row[1]; h2 += row[2]; h3 += row[3]; h4 += row[4];
+        h5 += row[5]; h6 += row[6]; h7 += row[7]; h8 += row[8];
+    }
+    hist[0] = h0; hist[1] = h1; hist[2] = h2; hist[3] = h3; hist[4] = h4;
+    hist[5] = h5; hist[6] = h6; hist[7] = h7; hist[8] = h8;
 }
 
 int ora_series(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0, int64_t n,
@@ -532,7 +560,7 @@ int ora_series(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0, int64
     for (i = 0; i < n; i++) {
         int rc = ora_sweep(s, model, L, seed, t0 + i, 1, beta, D, 1, NULL, NULL);
         if (rc) return rc;
-        ora_measure(s, L, &Bs[i], &Ms[i], &Qs[i], cnt);
+        ora_measure(s, L, &Bs[i], &Ms[i], &Qs[i], cnt, 1);
     }
     return 0;
 }

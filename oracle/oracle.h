@@ -68,9 +68,10 @@ int  ora_sweep(int8_t* s, int model, int64_t L, uint64_t seed, int64_t t0,
                int64_t n, double beta, double D, int nthreads,
                int64_t* dB, int64_t* dQ);
 
-/* B = sum s(x,y)[s(x+1,y)+s(x,y+1)], M = sum s, Q = sum s^2, counts of -1,0,+1. */
+/* B = sum s(x,y)[s(x+1,y)+s(x,y+1)], M = sum s, Q = sum s^2, counts of -1,0,+1.
+ * nthreads > 1 splits the rows over OpenMP threads (same integer sums). */
 void ora_measure(const int8_t* s, int64_t L, int64_t* B, int64_t* M, int64_t* Q,
-                 int64_t counts[3]);
+                 int64_t counts[3], int nthreads);
 
 /* Distances of the correlation function (section 3.3).  Returns the number
  * of distances, or -(needed) if cap is too small. */
@@ -78,12 +79,13 @@ int  ora_rset(int mode, int64_t L, int64_t t, int32_t* r, int cap);
 int64_t ora_rc(int64_t L, int64_t t);
 double  ora_g(int64_t L);
 
-/* S_a(r) = sum over sources p of s(p) s(p + r e_a), a in {x, y}. */
+/* S_a(r) = sum over sources p of s(p) s(p + r e_a), a in {x, y}; nthreads as
+ * for ora_measure. */
 void ora_corr(const int8_t* s, int64_t L, int mode, const int32_t* r, int nr,
-              int64_t* Cx, int64_t* Cy, int64_t* nsrc);
+              int64_t* Cx, int64_t* Cy, int64_t* nsrc, int nthreads);
 
 /* Schwinger-Dyson histogram: hist[k] = #sites with sigma*h = k - 4. */
-void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9]);
+void ora_sd_hist(const int8_t* s, int64_t L, int64_t hist[9], int nthreads);
 
 /* Light-cone windows of a large lattice.  patch[P*P] holds the sites
  * (x0 + i, y0 + j) mod L of an L x L lattice (row j, column i).  The

@@ -73,8 +73,8 @@ MUTANTS = [
      "b += v * at(s, L, x + 1, y);"),
     ("Q as sum of s", "q += v * v;", "q += v;"),
     ("correlation axes transposed", "sy += v * at(s, L, x, y + d);", "sy += v * at(s, L, x + d, y);"),
-    ("sampled sources one axis", "if (sampled && ((x % CORR_R) != 0 || (y % CORR_R) != 0)) continue;",
-     "if (sampled && (x % CORR_R) != 0) continue;"),
+    ("sampled sources one axis", "if (sampled && (y % CORR_R) != 0) continue;",
+     "if (sampled && (y % 1) != 0) continue;"),
     ("every-source range exclusive", "for (v = 0; v <= half && v <= 2 * CORR_R; v++)",
      "for (v = 0; v <= half && v < 2 * CORR_R; v++)"),
     ("r_c not rounded", "floor(ora_g(L) * sqrt((double)t) + 0.5)", "floor(ora_g(L) * sqrt((double)t))"),
@@ -82,7 +82,7 @@ MUTANTS = [
     # (d >= rc instead of d > rc in the log-spaced set is no mistake: a log-spaced
     # d equal to r_c is already the last distance of the linear part)
     ("log-spaced set from 2R", "if (d > rc && d <= half)", "if (d > 2 * CORR_R && d <= half)"),
-    ("sigma h histogram sign", "hist[v * h + 4]++;", "hist[-v * h + 4]++;"),
+    ("sigma h histogram sign", "row[v * h + 4]++;", "row[-v * h + 4]++;"),
     # the light-cone window (what the full-size GPU tests compare against)
     ("window ising always-flip bound", "int flip = aligned <= 2;\n                        if (!flip) flip = ora_accept",
      "int flip = aligned <= 1;\n                        if (!flip) flip = ora_accept"),
