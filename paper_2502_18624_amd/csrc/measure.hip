@@ -665,7 +665,7 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
 }
 
 // Along y, target-row order: block (residue rho, list chunk, band of rows,
-// source chunk).  Target row y' = rho + 16 k pairs with source row
+// source chunk of acw columns).  Target row y' = rho + 16 k pairs with source row
 // b = (y' - r) / 16 for every sampled r = rho (mod 16); the positions of
 // those r in the distance list are res_idx[res_off[rho] ..].  Thread t holds
 // the 4 targets (16 a, y') for a = a0 + 4 t .. + 3 as packed int8.
@@ -678,7 +678,8 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
                                                       const int32_t* __restrict__ rlist,
                                                       const int32_t* __restrict__ res_off,
                                                       const int32_t* __restrict__ res_idx, uint32_t nchunk,
-                                                      uint32_t nband, uint32_t nachunk, int64_t* __restrict__ Cy)
+                                                      uint32_t nband, uint32_t nachunk, uint32_t acw,
+                                                      int64_t* __restrict__ Cy)
 {
     const uint32_t W = L >> Cell<CB>::kWordShift;
     const uint32_t NS = L >> 4;                             // sources per row
@@ -697,8 +698,9 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
     const int p0 = res_off[rho] + (int)(chunk * kYChunk);
     const int p1 = res_off[rho + 1];
     if (p0 >= p1) return;
-    const uint32_t a0 = ac * 1024u + 4u * threadIdx.x;     // first of this thread's 4 columns
-    const bool live = a0 < NS;                              // NS is a multiple of 4
+    // a chunk holds acw source columns (a multiple of 4, at most 4 per thread)
+    const uint32_t a0 = ac * acw + 4u * threadIdx.x;        // first of this thread's 4 columns
+    const bool live = 4u * threadIdx.x < acw && a0 < NS;    // NS is a multiple of 4
     const size_t plane_words = (size_t)L * W;
     int acc[kYChunk];
     // r = rho + 16 m for every distance of this residue: the source row of
@@ -774,11 +776,37 @@ hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s)
 // Persistent kernels use at most this many workgroups (a few per CU).
 constexpr uint32_t kMaxGrid = 2048;
 
+// Optional cap on the workgroups of the persistent measurement kernels
+// (B/M/Q pass, short-distance tiles, sampled x rows): the environment
+// variable MCL_MEASURE_GRID, read at every launch.  It changes how the work
+// is split over workgroups, never the sums; a test uses it to give each
+// workgroup several tasks, tiles and rows at small L.
+uint32_t grid_cap(uint32_t want)
+{
+    if (const char* e = std::getenv("MCL_MEASURE_GRID")) {
+        const long long v = std::atoll(e);
+        if (v > 0 && (uint64_t)v < want) return (uint32_t)v;
+    }
+    return want;
+}
+
+// Source columns per y-correlation workgroup: 1024 (4 per thread), or the
+// multiple of 4 in MCL_SY_CHUNK (read at every launch) when smaller.
+uint32_t sy_chunk()
+{
+    uint32_t w = 1024;
+    if (const char* e = std::getenv("MCL_SY_CHUNK")) {
+        const long long v = std::atoll(e);
+        if (v >= 4 && v < 1024 && (v % 4) == 0) w = (uint32_t)v;
+    }
+    return w;
+}
+
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s)
 {
     const int64_t rows = pick_rows(g.L, 16);
     const int64_t threads = g.Q * (g.L / rows);
-    const uint32_t grid = (uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid);
+    const uint32_t grid = grid_cap((uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid));
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
     if (model == 2)
         hipLaunchKernelGGL(bmq_kernel<2>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
@@ -795,7 +823,7 @@ hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64
     const uint32_t Wp = (uint32_t)(g.L >> 6);
     const uint32_t nstrips = (Wp + kSW - 1) / kSW;
     const uint32_t ntiles = nstrips * (uint32_t)(g.L / kTH);
-    const dim3 grid(std::min<uint32_t>(ntiles, 1024));
+    const dim3 grid(grid_cap(std::min<uint32_t>(ntiles, 1024)));
     const uint32_t L = (uint32_t)g.L;
     if (model == 0)
         hipLaunchKernelGGL((corr_short_kernel<0>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
@@ -851,7 +879,7 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     // along x: LDS holds the distance sums of a launch, the source residue
     // and a group of G residue rows (P = L / 16 bytes each)
     const size_t P = nb, budget = sx_lds_budget();
-    const uint32_t gx = std::min<uint32_t>(nb, 512);
+    const uint32_t gx = grid_cap(std::min<uint32_t>(nb, 512));
     // 8 bytes per distance (its sum and its value)
     uint32_t G = 16;
     while (G > 1 && 8u * 64u + P * (1 + G) > budget) G >>= 1;
@@ -875,11 +903,12 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     }
     const uint32_t nchunk = (uint32_t)((a.max_per_residue + kYChunk - 1) / kYChunk);
     const uint32_t nband = (nb + kYRows - 1) / kYRows;
-    const uint32_t nachunk = (nb + 1023) / 1024;
+    const uint32_t acw = sy_chunk();
+    const uint32_t nachunk = (nb + acw - 1) / acw;
     if (nchunk == 0) return hipSuccess;
     const uint32_t nsy = nchunk * nband * nachunk;
     hipLaunchKernelGGL(corr_sy_kernel<CB>, dim3(128u * ((nsy + 7) / 8)), dim3(256), 0, s, g.plane0, L, a.zs, a.r,
-                       a.res_off, a.res_idx, nchunk, nband, nachunk, a.Cy);
+                       a.res_off, a.res_idx, nchunk, nband, nachunk, acw, a.Cy);
     return hipGetLastError();
 }
 
