@@ -204,37 +204,53 @@ int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, i
 
 /* Batched path: advance `count` independent lattices (any mix of
  * models, sizes, beta and D) by n[i] sweeps each.  Replicas advance sweep by
- * sweep together: one launch per model and colour covers every replica
- * (each workgroup belongs to one replica, so its parameters are
- * wave-uniform).  All lattices must use the stream of hs[0], and no two
- * entries with n[i] > 0 may share device memory (the same handle twice, or
- * handles on overlapping buffers), which would race: MCL_EARG otherwise,
- * before anything is queued.  Every lattice ends bit-identical to n[i]
- * sweep() calls on it alone, whatever the tuning.  1-bit lattices (MCL_ISING_LUT) advance
- * through sweep() within the call.  MCL_ERANGE if the replicas of one model
- * need more than 2^24 workgroups (2^32 work-items) in one launch.  The
- * library keeps a few small workspaces of its own (descriptors, pinned
- * staging, captured graphs), allocated on first use and grown when a larger
- * group arrives; they are never freed. */
+ * sweep together.  Every lattice of L <= 2^17 with n[i] > 0 goes into one
+ * launch per colour per sweep that covers all of them, all three models
+ * alike (or, with the split_models tuning, one launch per model and
+ * colour): a persistent grid walks a list of tiles of 256 threads, each
+ * tile one band of rows of one replica, so a replica's parameters are
+ * wave-uniform.  Larger lattices fill the GPU alone and are swept one per
+ * launch within the call.  All lattices must use the stream of hs[0], and
+ * no two entries with n[i] > 0 may share device memory (the same handle
+ * twice, or handles on overlapping buffers), which would race: MCL_EARG
+ * otherwise, before anything is queued.  Every lattice ends bit-identical
+ * to n[i] sweep() calls on it alone, whatever the tuning.  The launches of
+ * a call shape seen before are replayed from an executable HIP graph of
+ * graph_sweeps sweeps (captured on the second sighting; not while the
+ * caller captures the stream).  MCL_ERANGE if a launch would need more than
+ * 2^24 workgroups.  The library keeps a few small workspaces of its own
+ * (descriptors, pinned staging, captured graphs), allocated on first use
+ * and grown when a larger group arrives; they are never freed. */
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n,
                 const double* beta, const double* D);
 
 /* Tuning of group_sweep, process-wide; chosen by the package's autotuner.
- * rows_log2L[k]: band height (rows per thread, one of 8, 16, 32, 64) for
- * lattices with 2^k <= L < 2^(k+1); use_graph: capture the call's launches
- * in a hipGraph and replay it (cached per group shape); largest_first:
- * dispatch the largest replicas first.  Results never depend on it. */
+ * Results never depend on it.
+ *   rows_log2L[k] : band height (rows per thread: 8, 16, 32 or 64) for
+ *                   lattices with 2^k <= L < 2^(k+1);
+ *   use_graph     : replay repeated call shapes from captured graphs;
+ *   largest_first : order each launch's tile list by decreasing L (else
+ *                   call order);
+ *   wg_per_cu     : persistent grid of wg_per_cu workgroups per compute unit
+ *                   (1..32), or 0 for one workgroup per tile;
+ *   split_models  : one launch per model and colour instead of one per colour
+ *                   (each launch then holds one model's code path and
+ *                   register budget);
+ *   graph_sweeps  : sweeps per captured graph (1..64). */
 typedef struct mcl_group_tuning {
     int32_t rows_log2L[21];
     int32_t use_graph;
     int32_t largest_first;
+    int32_t wg_per_cu;
+    int32_t split_models;
+    int32_t graph_sweeps;
 } mcl_group_tuning;
 int mcl_group_tuning_get(mcl_group_tuning* out);
-int mcl_group_tuning_set(const mcl_group_tuning* in);   /* MCL_EARG on an invalid row count */
+int mcl_group_tuning_set(const mcl_group_tuning* in);   /* MCL_EARG on a value out of range */
 
-/* Release a handle (does not free the caller's device memory).  A handle
- * whose sweeps were replayed from graphs first waits for its stream, then
- * destroys the graphs. */
+/* Release a handle (does not free the caller's device memory).  Waits for
+ * the handle's stream first, so the buffer is free for reuse on return,
+ * then destroys the handle's graphs. */
 int lattice_free(mcl_lattice* h);
 
 const char* mcl_strerror(int code);

@@ -45,7 +45,8 @@ class MeasureOut(ctypes.Structure):
 
 class GroupTuning(ctypes.Structure):
     _fields_ = [("rows_log2L", ctypes.c_int32 * 21), ("use_graph", ctypes.c_int32),
-                ("largest_first", ctypes.c_int32)]
+                ("largest_first", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("split_models", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32)]
 
 
 # Every entry point of include/mcl.h with its ctypes signature.

@@ -1,8 +1,10 @@
 """Autotuner of the batched path.
 
-The tunables of ``group_sweep`` -- band height per lattice size, hipGraph
-capture, dispatch order -- change how the work is laid on the chip, never
-what it computes: the draws are keyed by the logical site.  The tuner
+The tunables of ``group_sweep`` -- band height per lattice size, the
+persistent grid (workgroups per compute unit, or one per tile), one launch
+per colour for every model or one per model, hipGraph replay, tile order --
+change how the work is laid on the chip, never what it computes: the draws
+are keyed by the logical site.  The tuner
 therefore times candidates on scratch lattices with the same (model, L) mix
 as the real group (same shapes, their own seeds), leaves the real lattices
 untouched, and installs the fastest setting process-wide.  Results are
@@ -31,16 +33,25 @@ def set_tuning(t: GroupTuning) -> None:
     check(lib().mcl_group_tuning_set(ctypes.byref(t)), "mcl_group_tuning_set")
 
 
+FIELDS = ("use_graph", "largest_first", "wg_per_cu", "split_models", "graph_sweeps")
+# candidate values of the scalar fields, searched after the band heights
+CHOICES = {"wg_per_cu": (0, 2, 4, 8), "split_models": (0, 1), "use_graph": (0, 1), "largest_first": (0, 1)}
+
+
 def tuning_dict(t: GroupTuning) -> dict:
-    return {"rows_log2L": list(t.rows_log2L), "use_graph": int(t.use_graph), "largest_first": int(t.largest_first)}
+    d = {"rows_log2L": list(t.rows_log2L)}
+    for f in FIELDS:
+        d[f] = int(getattr(t, f))
+    return d
 
 
 def tuning_from_dict(d: dict) -> GroupTuning:
-    t = GroupTuning()
+    t = get_tuning()
     for k, v in enumerate(d["rows_log2L"]):
         t.rows_log2L[k] = int(v)
-    t.use_graph = int(d["use_graph"])
-    t.largest_first = int(d["largest_first"])
+    for f in FIELDS:
+        if f in d:
+            setattr(t, f, int(d[f]))
     return t
 
 
@@ -103,15 +114,18 @@ def autotune_group(shapes, sweeps_per_call=8, reps=2, beta=0.44, D=0.5, verbose=
                 print("  rows[2^%d]=%d: %.3f ms" % (b, r, el * 1e3))
             if el < best_t:
                 best_t, cur = el, cand
-    for field in ("use_graph", "largest_first"):
-        cand = tuning_from_dict(tuning_dict(cur))
-        setattr(cand, field, 1 - getattr(cur, field))
-        set_tuning(cand)
-        el = _time_group(lats, sweeps_per_call, betas, Ds, reps)
-        if verbose:
-            print("  %s=%d: %.3f ms" % (field, getattr(cand, field), el * 1e3))
-        if el < best_t:
-            best_t, cur = el, cand
+    for field, values in CHOICES.items():
+        for v in values:
+            if v == getattr(cur, field):
+                continue
+            cand = tuning_from_dict(tuning_dict(cur))
+            setattr(cand, field, v)
+            set_tuning(cand)
+            el = _time_group(lats, sweeps_per_call, betas, Ds, reps)
+            if verbose:
+                print("  %s=%d: %.3f ms" % (field, v, el * 1e3))
+            if el < best_t:
+                best_t, cur = el, cand
     set_tuning(cur)
     for l in lats:
         l.free()

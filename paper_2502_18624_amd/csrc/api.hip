@@ -220,49 +220,35 @@ void spin_to_cell(uint32_t* row, int64_t i, int s, int cb)
 // ---------------------------------------------------------------------------
 // Batched path.
 // ---------------------------------------------------------------------------
+// Lattices up to this size go into the batched launches; larger ones fill
+// the GPU on their own and are swept one per launch.
+constexpr int64_t kGroupMaxL = int64_t(1) << 17;
+
 mcl_group_tuning default_tuning()
 {
     mcl_group_tuning t;
     for (int k = 0; k < 21; ++k) t.rows_log2L[k] = k >= 12 ? 32 : 16;
-    t.use_graph = 0;
+    t.use_graph = 1;
     t.largest_first = 1;
+    t.wg_per_cu = 0;
+    t.split_models = 0;
+    t.graph_sweeps = 32;
     return t;
+}
+
+bool valid_tuning(const mcl_group_tuning& t)
+{
+    for (int k = 0; k < 21; ++k) {
+        const int r = t.rows_log2L[k];
+        if (r != 8 && r != 16 && r != 32 && r != 64) return false;
+    }
+    return t.wg_per_cu >= 0 && t.wg_per_cu <= 32 && t.graph_sweeps >= 1 && t.graph_sweeps <= 64 &&
+           (t.use_graph == 0 || t.use_graph == 1) && (t.largest_first == 0 || t.largest_first == 1) &&
+           (t.split_models == 0 || t.split_models == 1);
 }
 
 std::mutex g_group_mu;
 mcl_group_tuning g_tuning = default_tuning();
-
-// A staging slot: pinned host buffer and device buffer for one call's
-// descriptors and tables, and an event recorded after the call's last
-// launch; a slot is reused only after that event completed, so neither
-// buffer is overwritten while a copy or kernel still reads it.
-struct Slot {
-    void* host = nullptr;
-    void* dev = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-};
-constexpr int kSlots = 4;
-struct DeviceSlots {
-    Slot slot[kSlots];
-    int next = 0;
-};
-std::map<int, DeviceSlots> g_slots;
-
-// Captured graphs, keyed by the call's shape (descriptor buffer, replica
-// counts, workgroup counts, sweeps).
-using GraphKey = std::tuple<void*, int, int, uint32_t, uint32_t, int64_t>;
-std::map<GraphKey, hipGraphExec_t> g_graphs;
-
-// Graph capture is not allowed on the null stream, which is where a caller
-// on PyTorch's default stream queues its work; such calls capture and
-// replay on a library stream (default priority) fenced by events.
-struct CaptureStream {
-    hipStream_t stream = nullptr;
-    hipEvent_t in = nullptr, out = nullptr;
-};
-std::map<int, CaptureStream> g_capture;
 
 int log2_floor(int64_t v)
 {
@@ -290,6 +276,232 @@ void bc_lds_table(double beta, double D, uint32_t* out /* 192 words */)
     }
 }
 
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int compute_units(int dev)
+{
+    static std::map<int, int> cache;
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
+
+// The launches of one batched call and the device image they read:
+// descriptors (launch by launch), Blume-Capel tables, 1-bit records and the
+// word a captured graph adds its sweep offset to.
+struct GroupLaunch {
+    int mask;          // models in the launch (kMask*)
+    size_t first;      // its first descriptor
+    int count;
+    uint32_t total;    // tiles
+    uint32_t grid;     // workgroups (a multiple of 8)
+};
+struct GroupImage {
+    std::vector<GroupLaunch> launches;
+    size_t ndesc = 0, nbc = 0, nlut = 0;
+    size_t off_bc = 0, off_lut = 0, off_s = 0, bytes = 0;
+    int64_t nmax = 0;
+};
+
+// Replicas of the batched launches: n > 0 and L <= kGroupMaxL.
+bool batched(const mcl_lattice* h, int64_t n) { return n > 0 && h->L <= kGroupMaxL; }
+
+// Plan the call (launches, tiles, grid) into `img`; when `host` is given,
+// also write the image there (it must hold img.bytes).  MCL_ERANGE if a
+// launch would need more than 2^24 workgroups or 2^32 tiles.
+int group_layout(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D,
+                 const mcl_group_tuning& tun, int cus, GroupImage& img, void* host)
+{
+    img = GroupImage();
+    std::vector<int> by[3];
+    for (int i = 0; i < count; ++i)
+        if (batched(hs[i], n[i])) {
+            by[tun.split_models ? hs[i]->model : 0].push_back(i);
+            img.nmax = std::max(img.nmax, n[i]);
+            img.ndesc++;
+            img.nbc += hs[i]->model == MCL_BC;
+            img.nlut += hs[i]->model == MCL_ISING_LUT;
+        }
+    img.off_bc = align_up(img.ndesc * sizeof(mcl::GroupDesc), 256);
+    img.off_lut = align_up(img.off_bc + img.nbc * 96 * sizeof(uint2), 256);
+    img.off_s = align_up(img.off_lut + img.nlut * sizeof(mcl::LutRec), 256);
+    img.bytes = img.off_s + 256;
+    char* base = (char*)host;
+    mcl::GroupDesc* hd = (mcl::GroupDesc*)base;
+    uint32_t* htab = base ? (uint32_t*)(base + img.off_bc) : nullptr;
+    mcl::LutRec* hlut = base ? (mcl::LutRec*)(base + img.off_lut) : nullptr;
+    size_t k = 0, nb = 0, nl = 0;
+    for (int m = 0; m < 3; ++m) {
+        std::vector<int>& idx = by[m];
+        if (idx.empty()) continue;
+        if (tun.largest_first)
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return hs[a]->L > hs[b]->L; });
+        GroupLaunch ln{0, k, (int)idx.size(), 0, 0};
+        uint64_t tiles = 0;
+        for (int i : idx) {
+            const mcl_lattice* h = hs[i];
+            const uint32_t rows = (uint32_t)tun.rows_log2L[log2_floor(h->L)];
+            const int64_t threads = h->g.Q * (h->L / rows);
+            ln.mask |= h->model == MCL_ISING ? mcl::kMaskIsing : h->model == MCL_BC ? mcl::kMaskBC : mcl::kMaskLut;
+            if (base) {
+                mcl::GroupDesc d;
+                std::memset(&d, 0, sizeof(d));
+                d.plane0 = h->g.plane0;
+                d.L = (uint32_t)h->L;
+                d.rows = rows;
+                d.t0 = (uint32_t)h->t;
+                d.n = (uint32_t)n[i];
+                d.k0 = (uint32_t)h->seed;
+                d.k1 = (uint32_t)(h->seed >> 32);
+                d.tile_begin = (uint32_t)tiles;
+                d.model = (uint32_t)h->model;
+                if (h->model == MCL_ISING) {
+                    ising_thresholds(beta[i], d.T4, d.T8);
+                } else if (h->model == MCL_BC) {
+                    d.tab = (uint32_t)nb;
+                    bc_lds_table(beta[i], D[i], htab + nb * 192);
+                } else {
+                    d.tab = (uint32_t)nl;
+                    const mcl::LutTable lt = lut_device_table(beta[i]);
+                    mcl::LutRec r;
+                    std::memset(&r, 0, sizeof(r));
+                    r.buckets = (uint2*)h->lutb;
+                    std::memcpy(r.T, lt.T, sizeof(r.T));
+                    r.kmax = lt.kmax;
+                    hlut[nl] = r;
+                }
+                hd[k] = d;
+            }
+            nb += h->model == MCL_BC;
+            nl += h->model == MCL_ISING_LUT;
+            ++k;
+            tiles += (uint64_t)((threads + 255) / 256);
+        }
+        if (tiles >= (uint64_t(1) << 32)) return MCL_ERANGE;
+        ln.total = (uint32_t)tiles;
+        // one workgroup per tile, or a persistent grid of wg_per_cu per CU;
+        // a multiple of 8 either way (one share per XCD)
+        uint64_t grid = (tiles + 7) / 8 * 8;
+        if (tun.wg_per_cu > 0) grid = std::min<uint64_t>(grid, (uint64_t)cus * tun.wg_per_cu / 8 * 8);
+        grid = std::max<uint64_t>(grid, 8);
+        if (grid > (uint64_t(1) << 24)) return MCL_ERANGE;
+        ln.grid = (uint32_t)grid;
+        img.launches.push_back(ln);
+    }
+    return MCL_OK;
+}
+
+// Launches of sweeps [s0, s0 + k) of a planned call on stream st, the
+// image at `dev` (sbase: device word added to s, or nullptr).
+hipError_t group_launches(const GroupImage& img, const void* dev, int64_t s0, int64_t k, const uint32_t* sbase,
+                          hipStream_t st)
+{
+    const char* b = (const char*)dev;
+    const mcl::GroupDesc* desc = (const mcl::GroupDesc*)b;
+    const uint2* tabs = (const uint2*)(b + img.off_bc);
+    const mcl::LutRec* luts = (const mcl::LutRec*)(b + img.off_lut);
+    for (int64_t s = s0; s < s0 + k; ++s)
+        for (int c = 0; c < 2; ++c)
+            for (const GroupLaunch& ln : img.launches) {
+                const hipError_t e = mcl::launch_group_half(ln.mask, c, desc + ln.first, ln.count, ln.total, ln.grid,
+                                                            tabs, luts, (uint32_t)s, sbase, st);
+                if (e != hipSuccess) return e;
+            }
+    return hipSuccess;
+}
+
+// Work of a planned call whose image is already on its way to `dev` on
+// stream st: the 1-bit bucket tables, then the sweeps as plain launches.
+hipError_t group_plain(const GroupImage& img, const void* dev, hipStream_t st)
+{
+    hipError_t e = mcl::launch_group_lut_buckets((const mcl::LutRec*)((const char*)dev + img.off_lut), (int)img.nlut,
+                                                 st);
+    if (e != hipSuccess) return e;
+    return group_launches(img, dev, 0, img.nmax, nullptr, st);
+}
+
+// A staging slot: pinned host buffer and device buffer for one call's
+// image, and an event recorded after the call's last launch.  A slot is
+// reused only after that event completed, so at most one call per slot is
+// in flight and neither buffer is overwritten while a copy or kernel reads
+// it.  Graphs captured against the slot's device buffer live with the slot.
+struct SlotGraph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+struct Slot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    std::vector<SlotGraph> graphs;
+};
+constexpr int kSlots = 4;
+constexpr size_t kSlotGraphs = 8;
+struct DeviceSlots {
+    Slot slot[kSlots];
+    int next = 0;
+    std::vector<std::vector<uint64_t>> seen;      // recent call shapes (a graph is captured on a repeat)
+};
+std::map<int, DeviceSlots> g_slots;
+uint64_t g_graph_clock = 0;
+
+// Graph capture is not allowed on the null stream, which is where a caller
+// on PyTorch's default stream queues its work; such calls capture and
+// replay on a library stream (default priority) fenced by events.
+struct CaptureStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;
+};
+std::map<int, CaptureStream> g_capture;
+
+void destroy_graphs(Slot& sl)
+{
+    for (auto& g : sl.graphs) (void)hipGraphExecDestroy(g.exec);        // best effort: the slot is idle
+    sl.graphs.clear();
+}
+
+// The executable graph of k sweeps of the planned call on slot sl (sweep
+// index *sdev + i, then *sdev += k), captured on stream gs if absent.
+int slot_graph(Slot& sl, const GroupImage& img, int64_t k, hipStream_t gs, const std::vector<uint64_t>& key,
+               hipGraphExec_t* out)
+{
+    for (auto& g : sl.graphs)
+        if (g.key == key) {
+            g.last_use = ++g_graph_clock;
+            *out = g.exec;
+            return MCL_OK;
+        }
+    uint32_t* sdev = (uint32_t*)((char*)sl.dev + img.off_s);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MCL_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+    hipError_t le = group_launches(img, sl.dev, 0, k, sdev, gs);
+    if (le == hipSuccess) le = mcl::launch_set_word(sdev, (uint32_t)k, true, gs);
+    const hipError_t ce = hipStreamEndCapture(gs, &graph);
+    if (ce == hipSuccess && le != hipSuccess) (void)hipGraphDestroy(graph);
+    if (le != hipSuccess) return hip_fail(le);
+    if (ce != hipSuccess) return hip_fail(ce);
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);                       // the executable graph keeps what it needs
+    if (ie != hipSuccess) return hip_fail(ie);
+    if (sl.graphs.size() >= kSlotGraphs) {
+        // least recently used; the slot is idle (its last call completed), so is the graph
+        auto lru = std::min_element(sl.graphs.begin(), sl.graphs.end(),
+                                    [](const SlotGraph& a, const SlotGraph& b) { return a.last_use < b.last_use; });
+        (void)hipGraphExecDestroy(lru->exec);
+        sl.graphs.erase(lru);
+    }
+    sl.graphs.push_back({key, exec, ++g_graph_clock});
+    *out = exec;
+    return MCL_OK;
+}
+
 int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
 {
     std::lock_guard<std::mutex> lk(g_group_mu);
@@ -297,22 +509,10 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
     hipStream_t stream = hs[0]->stream;
     int devid = 0;
     MCL_HIP(hipGetDevice(&devid));
-
-    // replicas with work, per model, optionally largest first
-    std::vector<int> idx[2];
-    int64_t nmax = 0;
-    for (int i = 0; i < count; ++i)
-        if (n[i] > 0 && hs[i]->model <= MCL_BC) {
-            idx[hs[i]->model].push_back(i);
-            nmax = std::max(nmax, n[i]);
-        }
-    if (nmax == 0) return MCL_OK;
-    for (int m = 0; m < 2; ++m)
-        if (tun.largest_first)
-            std::stable_sort(idx[m].begin(), idx[m].end(), [&](int a, int b) { return hs[a]->L > hs[b]->L; });
-
-    const size_t ndesc = idx[0].size() + idx[1].size();
-    const size_t bytes = ndesc * sizeof(mcl::GroupDesc) + idx[1].size() * 96 * sizeof(uint2);
+    GroupImage img;
+    int rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, nullptr);
+    if (rc) return rc;
+    if (img.nmax == 0) return MCL_OK;
 
     DeviceSlots& ds = g_slots[devid];
     Slot& sl = ds.slot[ds.next];
@@ -322,76 +522,51 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
         sl.pending = false;
     }
     if (!sl.done) MCL_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    if (sl.cap < bytes) {
-        // graphs captured against the old device buffer are dropped with it
-        for (auto it = g_graphs.begin(); it != g_graphs.end();) {
-            if (std::get<0>(it->first) == sl.dev) {
-                (void)hipGraphExecDestroy(it->second);          // best effort: the buffer goes with it
-                it = g_graphs.erase(it);
-            } else {
-                ++it;
-            }
-        }
+    if (sl.cap < img.bytes) {
+        destroy_graphs(sl);                               // they read the old device buffer
         if (sl.host) MCL_HIP(hipHostFree(sl.host));
         if (sl.dev) MCL_HIP(hipFree(sl.dev));
         sl.host = sl.dev = nullptr;
         sl.cap = 0;
-        const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
+        const size_t cap = std::max<size_t>(img.bytes * 2, 64 * 1024);
         MCL_HIP(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
         MCL_HIP(hipMalloc(&sl.dev, cap));
         sl.cap = cap;
     }
+    rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, sl.host);
+    if (rc) return rc;
+    // the sweep-offset word starts at 0 (graph replays add to it)
+    std::memset((char*)sl.host + img.off_s, 0, 256);
+    MCL_HIP(hipMemcpyAsync(sl.dev, sl.host, img.bytes, hipMemcpyHostToDevice, stream));
 
-    mcl::GroupDesc* hd = (mcl::GroupDesc*)sl.host;
-    uint32_t* htab = (uint32_t*)(hd + ndesc);
-    uint32_t wgs[2] = {0, 0};
-    int nb = 0;
-    size_t k = 0;
-    for (int m = 0; m < 2; ++m)
-        for (int i : idx[m]) {
-            const mcl_lattice* h = hs[i];
-            mcl::GroupDesc d;
-            std::memset(&d, 0, sizeof(d));
-            d.plane0 = h->g.plane0;
-            d.L = (uint32_t)h->L;
-            d.rows = (uint32_t)tun.rows_log2L[log2_floor(h->L)];
-            d.hi0 = (h->L * h->L / 8) <= (int64_t(1) << 32) ? 1u : 0u;
-            d.t0 = (uint32_t)h->t;
-            d.n = (uint32_t)n[i];
-            d.k0 = (uint32_t)h->seed;
-            d.k1 = (uint32_t)(h->seed >> 32);
-            if (m == 0) {
-                ising_thresholds(beta[i], d.T4, d.T8);
-            } else {
-                d.bc = (uint32_t)nb;
-                bc_lds_table(beta[i], D[i], htab + (size_t)nb * 192);
-                ++nb;
-            }
-            const int64_t threads = h->g.Q * (h->L / d.rows);
-            d.wg_begin = wgs[m];
-            // one launch covers at most 2^32 work-items (2^24 workgroups)
-            if ((int64_t)wgs[m] + (threads + 255) / 256 > (int64_t(1) << 24)) return MCL_ERANGE;
-            wgs[m] += (uint32_t)((threads + 255) / 256);
-            hd[k++] = d;
+    // graph replays for a shape seen before (and not inside a capture of the caller's)
+    const int64_t K = std::min<int64_t>(tun.graph_sweeps, img.nmax);
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(stream, &cst) != hipSuccess || cst != hipStreamCaptureStatusNone;
+    bool use_graph = tun.use_graph && !capturing && img.nmax >= 2;
+    std::vector<uint64_t> key;
+    if (use_graph) {
+        key = {(uint64_t)(uintptr_t)sl.dev, (uint64_t)K, (uint64_t)img.off_bc, (uint64_t)img.off_lut,
+               (uint64_t)img.off_s};
+        for (const GroupLaunch& ln : img.launches)
+            key.insert(key.end(), {(uint64_t)ln.mask, (uint64_t)ln.first, (uint64_t)ln.count, (uint64_t)ln.total,
+                                   (uint64_t)ln.grid});
+        // a shape is captured the second time it is seen: one-off shapes run plain
+        std::vector<uint64_t> shape(key.begin() + 1, key.end());
+        const bool known = std::any_of(sl.graphs.begin(), sl.graphs.end(),
+                                       [&](const SlotGraph& g) { return g.key == key; });
+        const bool seen = std::find(ds.seen.begin(), ds.seen.end(), shape) != ds.seen.end();
+        if (!seen) {
+            ds.seen.push_back(shape);
+            if (ds.seen.size() > 16) ds.seen.erase(ds.seen.begin());
         }
-    MCL_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
-    const mcl::GroupDesc* ddesc[2] = {(const mcl::GroupDesc*)sl.dev,
-                                      (const mcl::GroupDesc*)sl.dev + idx[0].size()};
-    const uint2* dtab = (const uint2*)((const mcl::GroupDesc*)sl.dev + ndesc);
-    const int cnt[2] = {(int)idx[0].size(), (int)idx[1].size()};
-
-    auto launch_all = [&]() -> hipError_t {
-        for (int64_t s = 0; s < nmax; ++s)
-            for (int c = 0; c < 2; ++c)
-                for (int m = 0; m < 2; ++m) {
-                    const hipError_t e = mcl::launch_group_half(m, c, ddesc[m], cnt[m], wgs[m], dtab,
-                                                                (uint32_t)s, stream);
-                    if (e != hipSuccess) return e;
-                }
-        return hipSuccess;
-    };
-
-    if (tun.use_graph && nmax > 1) {
+        use_graph = known || seen;
+    }
+    if (!use_graph) {
+        MCL_HIP(group_plain(img, sl.dev, stream));
+    } else {
+        MCL_HIP(mcl::launch_group_lut_buckets((const mcl::LutRec*)((const char*)sl.dev + img.off_lut), (int)img.nlut,
+                                              stream));
         hipStream_t gs = stream;
         CaptureStream* cs = nullptr;
         if (stream == nullptr) {
@@ -405,37 +580,17 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
             MCL_HIP(hipEventRecord(cs->in, stream));
             MCL_HIP(hipStreamWaitEvent(gs, cs->in, 0));
         }
-        const GraphKey key{sl.dev, cnt[0], cnt[1], wgs[0], wgs[1], nmax};
-        auto it = g_graphs.find(key);
-        if (it == g_graphs.end()) {
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            MCL_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
-            hipError_t le = hipSuccess;
-            for (int64_t s = 0; s < nmax && le == hipSuccess; ++s)
-                for (int c = 0; c < 2 && le == hipSuccess; ++c)
-                    for (int m = 0; m < 2 && le == hipSuccess; ++m)
-                        le = mcl::launch_group_half(m, c, ddesc[m], cnt[m], wgs[m], dtab, (uint32_t)s, gs);
-            const hipError_t ce = hipStreamEndCapture(gs, &graph);
-            if (ce == hipSuccess && le != hipSuccess) (void)hipGraphDestroy(graph);
-            if (le != hipSuccess) return hip_fail(le);
-            if (ce != hipSuccess) return hip_fail(ce);
-            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);                       // the executable graph keeps what it needs
-            if (ie != hipSuccess) return hip_fail(ie);
-            if (g_graphs.size() >= 32) {
-                (void)hipGraphExecDestroy(g_graphs.begin()->second);
-                g_graphs.erase(g_graphs.begin());
-            }
-            it = g_graphs.emplace(key, exec).first;
-        }
-        MCL_HIP(hipGraphLaunch(it->second, gs));
+        hipGraphExec_t exec = nullptr;
+        rc = slot_graph(sl, img, K, gs, key, &exec);
+        if (rc) return rc;
+        const int64_t reps = img.nmax / K;
+        for (int64_t r = 0; r < reps; ++r) MCL_HIP(hipGraphLaunch(exec, gs));
+        if (reps * K < img.nmax)
+            MCL_HIP(group_launches(img, sl.dev, reps * K, img.nmax - reps * K, nullptr, gs));
         if (cs) {
             MCL_HIP(hipEventRecord(cs->out, gs));
             MCL_HIP(hipStreamWaitEvent(stream, cs->out, 0));
         }
-    } else {
-        MCL_HIP(launch_all());
     }
     MCL_HIP(hipEventRecord(sl.done, stream));
     sl.pending = true;
@@ -664,9 +819,10 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
 int lattice_free(mcl_lattice* h)
 {
     if (!h) return MCL_EARG;
-    // replays of the lattice's graphs may still be queued: let them finish
-    if (!h->graphs.empty()) (void)hipStreamSynchronize(h->stream);
-    for (const auto& sg : h->graphs) (void)hipGraphExecDestroy(sg.exec);   // best effort: the handle goes
+    // work queued on the lattice (sweeps, graph replays) may still be running:
+    // let it finish before the caller can reuse the buffer or the graphs go
+    (void)hipStreamSynchronize(h->stream);                 // best effort: the handle goes either way
+    for (const auto& sg : h->graphs) (void)hipGraphExecDestroy(sg.exec);
     delete h;
     return MCL_OK;
 }
@@ -887,29 +1043,25 @@ int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const doubl
         if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
     }
     // entries that do work must not share device memory: their updates would
-    // run concurrently on the same cells
+    // run concurrently on the same cells (or on a 1-bit replica's bucket table)
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int i = 0; i < count; ++i)
         if (n[i] > 0) {
             const uintptr_t a = (uintptr_t)hs[i]->g.plane0;
-            spans.emplace_back(a, a + (uintptr_t)(2 * hs[i]->g.plane_words() * 4));
+            spans.emplace_back(a, a + (uintptr_t)layout_of(hs[i]->model, hs[i]->L).total);
         }
     std::sort(spans.begin(), spans.end());
     for (size_t k = 1; k < spans.size(); ++k)
         if (spans[k].first < spans[k - 1].second) return MCL_EARG;
-    // 1-bit replicas are advanced one lattice per launch after the batched
-    // launches of the 4-bit replicas (they are independent lattices)
-    std::vector<int64_t> n4(n, n + count);
-    for (int i = 0; i < count; ++i)
-        if (hs[i]->model == MCL_ISING_LUT) n4[i] = 0;
-    const int rc = group_run(hs, count, n4.data(), beta, D);
+    const int rc = group_run(hs, count, n, beta, D);
     if (rc) return rc;
     for (int i = 0; i < count; ++i) {
-        if (hs[i]->model == MCL_ISING_LUT) {
+        if (batched(hs[i], n[i])) {
+            hs[i]->t += n[i];
+        } else if (n[i] > 0) {
+            // a lattice larger than kGroupMaxL fills the GPU alone: one per launch
             const int r2 = sweep(hs[i], n[i], beta[i], D[i]);
             if (r2) return r2;
-        } else {
-            hs[i]->t += n[i];
         }
     }
     return MCL_OK;
@@ -925,11 +1077,7 @@ int mcl_group_tuning_get(mcl_group_tuning* out)
 
 int mcl_group_tuning_set(const mcl_group_tuning* in)
 {
-    if (!in) return MCL_EARG;
-    for (int k = 0; k < 21; ++k) {
-        const int r = in->rows_log2L[k];
-        if (r != 8 && r != 16 && r != 32 && r != 64) return MCL_EARG;
-    }
+    if (!in || !valid_tuning(*in)) return MCL_EARG;
     std::lock_guard<std::mutex> lk(g_group_mu);
     g_tuning = *in;
     return MCL_OK;

@@ -1,75 +1,181 @@
-// Batched half-sweep: many independent lattices -- any mix of
+// Batched half-sweep: many independent lattices -- any mix of models,
 // sizes, temperatures, crystal fields and seeds -- advance in one launch per
-// model and colour.  Each workgroup belongs to exactly one replica (its task
-// range is padded to whole workgroups), so the replica's parameters are
-// wave-uniform and the per-thread work is the one-lattice band update of
-// sweep_device.h: every lattice ends bit-identical to its own sweeps.
+// colour.  The work is a list of tiles of 256 threads; every tile belongs to
+// one replica, so the replica's parameters are wave-uniform, and the
+// per-thread work is the one-lattice band update of sweep_device.h: every
+// lattice ends bit-identical to its own sweeps.
+//
+// The grid is persistent: `grid` workgroups (a multiple of 8) walk the tile
+// list.  Workgroup ids go round-robin to the 8 XCDs, so the workgroups of
+// XCD x take the tiles of the x-th eighth of the list in turn; neighbouring
+// tiles of a replica (whose bands share halo rows) then run on one XCD and
+// meet in its L2.  A workgroup keeps the acceptance table of its current
+// replica in LDS and reloads it only when its next tile belongs to another
+// replica: the 96-entry Blume-Capel table, or the 32 KiB bucket table of a
+// 1-bit replica.
 #include "internal.h"
 #include "sweep_device.h"
 
 namespace mcl {
 namespace {
 
-// Replica of workgroup `wg`: last descriptor with wg_begin <= wg.
-__device__ __forceinline__ int find_replica(const GroupDesc* __restrict__ desc, int count, uint32_t wg)
+// Replica of tile `tile`: last descriptor with tile_begin <= tile.
+__device__ __forceinline__ int find_replica(const GroupDesc* __restrict__ desc, int count, uint32_t tile)
 {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (desc[mid].wg_begin <= wg) lo = mid;
+        if (desc[mid].tile_begin <= tile) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
-template <int MODEL, int COLOR>
-__global__ __launch_bounds__(256) void group_half_kernel(const GroupDesc* __restrict__ desc, int count,
-                                                         const uint2* __restrict__ tables, uint32_t s)
+struct LutLds {
+    uint2 b[dev::kLutBuckets];
+    uint32_t T[16];
+};
+
+// LDS of a launch: the Blume-Capel table, or (launches holding 1-bit
+// replicas) room for either table.
+template <bool LUT>
+union GroupLds;
+
+template <>
+union GroupLds<false> {
+    dev::BCLds bc;
+};
+
+template <>
+union GroupLds<true> {
+    dev::BCLds bc;
+    LutLds lut;
+};
+
+template <int MASK>
+__device__ __forceinline__ uint32_t model_of(uint32_t m)
 {
-    __shared__ dev::BCLds s_tab;
-    const int i = find_replica(desc, count, blockIdx.x);
-    const GroupDesc d = desc[i];
-    if (s >= d.n) return;
-    if (MODEL == 1) dev::load_bc_table(s_tab, tables + (size_t)d.bc * 96u);
-    const uint32_t L = d.L;
-    const uint32_t Q = L >> 6;
-    const uint32_t g = (blockIdx.x - d.wg_begin) * blockDim.x + threadIdx.x;
-    const uint32_t q = g % Q;
-    const uint32_t band = g / Q;
-    const uint32_t y0 = band * d.rows;
-    if (y0 >= L) return;
-    const size_t plane_words = (size_t)L * (L >> 4);
-    uint32_t* own = d.plane0 + (COLOR ? plane_words : 0);
-    const uint32_t* oth = d.plane0 + (COLOR ? 0 : plane_words);
-    // the thresholds feed scalar operands of the acceptance compares
-    const uint32_t T4 = __builtin_amdgcn_readfirstlane(d.T4);
-    const uint32_t T8 = __builtin_amdgcn_readfirstlane(d.T8);
-    const uint32_t t = d.t0 + s;
-    uint32_t hu;
-    const int hm = dev::counter_mode(d.hi0 != 0, ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2,
-                                     ((uint64_t)(y0 + d.rows - 1) * (L >> 1) + 32u * q + 31u) >> 2, hu);
-    if (hm == 0)
-        dev::band_update<MODEL, 0, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, s_tab.e);
-    else if (hm == 1)
-        dev::band_update<MODEL, 1, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, hu, T4, T8, s_tab.e);
+    return MASK == kMaskIsing ? 0u : MASK == kMaskBC ? 1u : MASK == kMaskLut ? 2u : m;
+}
+
+template <int MASK, int COLOR>
+__global__ __launch_bounds__(256) void group_half_kernel(const GroupDesc* __restrict__ desc, int count,
+                                                         const uint2* __restrict__ bc_tables,
+                                                         const LutRec* __restrict__ luts, uint32_t total,
+                                                         uint32_t s, const uint32_t* __restrict__ sbase)
+{
+    constexpr bool kLut = (MASK & kMaskLut) != 0;
+    __shared__ GroupLds<kLut> lds;
+    if (sbase) s += *sbase;
+    // a grid that is not a multiple of 8 walks the whole list round-robin
+    const bool by_xcd = (gridDim.x & 7u) == 0;
+    const uint32_t part = by_xcd ? (blockIdx.x & 7u) : 0u;
+    const uint32_t slot = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
+    const uint32_t step = by_xcd ? (gridDim.x >> 3) : gridDim.x;
+    const uint32_t seg_begin = by_xcd ? (uint32_t)((uint64_t)total * part / 8u) : 0u;
+    const uint32_t seg_end = by_xcd ? (uint32_t)((uint64_t)total * (part + 1u) / 8u) : total;
+    int cur = -1;                                   // replica whose table is in LDS
+    for (uint32_t tile = seg_begin + slot; tile < seg_end; tile += step) {
+        const int i = find_replica(desc, count, tile);
+        const GroupDesc d = desc[i];
+        if (s >= d.n) continue;                      // this replica has done its sweeps
+        const uint32_t model = model_of<MASK>(d.model);
+        if (model != 0u && i != cur) {
+            __syncthreads();                         // every wave is done with the old table
+            if ((MASK & kMaskBC) && model == 1u) {
+                dev::load_bc_table(lds.bc, bc_tables + (size_t)d.tab * 96u);
+            } else if constexpr (kLut) {
+                const LutRec* rec = luts + d.tab;
+                const uint4* src = reinterpret_cast<const uint4*>(rec->buckets);
+                uint4* dst = reinterpret_cast<uint4*>(lds.lut.b);
+                for (uint32_t k = threadIdx.x; k < (uint32_t)dev::kLutBuckets / 2; k += blockDim.x) dst[k] = src[k];
+                if (threadIdx.x < 16) lds.lut.T[threadIdx.x] = rec->T[threadIdx.x];
+                __syncthreads();
+            }
+            cur = i;
+        }
+        const uint32_t L = d.L;
+        const uint32_t t = d.t0 + s;
+        const uint32_t g = (tile - d.tile_begin) * 256u + threadIdx.x;
+        const size_t plane_words = (size_t)L * (L >> (model == 2u ? 6 : 4));
+        uint32_t* own = d.plane0 + (COLOR ? plane_words : 0);
+        const uint32_t* oth = d.plane0 + (COLOR ? 0 : plane_words);
+        if ((MASK & kMaskLut) && model == 2u) {
+            if constexpr (kLut) {
+                const uint32_t Q = L >> 8;
+                const uint32_t q = g % Q, y0 = (g / Q) * d.rows;
+                const LutRec* rec = luts + d.tab;
+                const uint32_t T8 = __builtin_amdgcn_readfirstlane(rec->T[8]);
+                const uint32_t kmax = __builtin_amdgcn_readfirstlane(rec->kmax);
+                if (y0 < L)
+                    dev::band_update_lut<0, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, lds.lut.b,
+                                                   lds.lut.T, T8, kmax);
+            }
+        } else {
+            const uint32_t Q = L >> 6;
+            const uint32_t q = g % Q, y0 = (g / Q) * d.rows;
+            // the thresholds feed scalar operands of the acceptance compares
+            const uint32_t T4 = __builtin_amdgcn_readfirstlane(d.T4);
+            const uint32_t T8 = __builtin_amdgcn_readfirstlane(d.T8);
+            if (y0 < L) {
+                if ((MASK & kMaskBC) && model == 1u)
+                    dev::band_update<1, 0, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, lds.bc.e);
+                else if (MASK & kMaskIsing)
+                    dev::band_update<0, 0, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, lds.bc.e);
+            }
+        }
+    }
+}
+
+// Bucket tables of the 1-bit replicas: block (b, r) writes 256 buckets of replica r.
+__global__ __launch_bounds__(256) void group_lut_bucket_kernel(const LutRec* __restrict__ luts)
+{
+    const LutRec* rec = luts + blockIdx.y;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= (uint32_t)dev::kLutBuckets) return;
+    const uint64_t A = dev::lut_bucket_addend(rec->T, rec->kmax, b);
+    rec->buckets[b] = make_uint2((uint32_t)A, (uint32_t)(A >> 32));
+}
+
+template <int MASK>
+void launch_mask(int color, dim3 grid, hipStream_t st, const GroupDesc* desc, int count, const uint2* tabs,
+                 const LutRec* luts, uint32_t total, uint32_t s, const uint32_t* sbase)
+{
+    if (color == 0)
+        hipLaunchKernelGGL((group_half_kernel<MASK, 0>), grid, dim3(256), 0, st, desc, count, tabs, luts, total, s,
+                           sbase);
     else
-        dev::band_update<MODEL, 2, COLOR>(own, oth, L, d.rows, q, y0, t, d.k0, d.k1, 0u, T4, T8, s_tab.e);
+        hipLaunchKernelGGL((group_half_kernel<MASK, 1>), grid, dim3(256), 0, st, desc, count, tabs, luts, total, s,
+                           sbase);
 }
 
 }  // namespace
 
-hipError_t launch_group_half(int model, int color, const GroupDesc* desc, int count, uint32_t total_wgs,
-                             const uint2* tables, uint32_t s, hipStream_t st)
+hipError_t launch_group_half(int mask, int color, const GroupDesc* desc, int count, uint32_t total, uint32_t grid,
+                             const uint2* bc_tables, const LutRec* luts, uint32_t s, const uint32_t* sbase,
+                             hipStream_t st)
 {
-    if (count <= 0 || total_wgs == 0) return hipSuccess;
-    const dim3 grid(total_wgs), blk(256);
-    if (model == 0) {
-        if (color == 0) hipLaunchKernelGGL((group_half_kernel<0, 0>), grid, blk, 0, st, desc, count, tables, s);
-        else hipLaunchKernelGGL((group_half_kernel<0, 1>), grid, blk, 0, st, desc, count, tables, s);
-    } else {
-        if (color == 0) hipLaunchKernelGGL((group_half_kernel<1, 0>), grid, blk, 0, st, desc, count, tables, s);
-        else hipLaunchKernelGGL((group_half_kernel<1, 1>), grid, blk, 0, st, desc, count, tables, s);
+    if (count <= 0 || total == 0 || grid == 0) return hipSuccess;
+    const dim3 g(grid);
+    switch (mask) {
+    case kMaskIsing: launch_mask<kMaskIsing>(color, g, st, desc, count, bc_tables, luts, total, s, sbase); break;
+    case kMaskBC: launch_mask<kMaskBC>(color, g, st, desc, count, bc_tables, luts, total, s, sbase); break;
+    case kMaskLut: launch_mask<kMaskLut>(color, g, st, desc, count, bc_tables, luts, total, s, sbase); break;
+    case kMaskIsing | kMaskBC:
+        launch_mask<kMaskIsing | kMaskBC>(color, g, st, desc, count, bc_tables, luts, total, s, sbase);
+        break;
+    default:
+        // any mix holding 1-bit replicas
+        launch_mask<kMaskIsing | kMaskBC | kMaskLut>(color, g, st, desc, count, bc_tables, luts, total, s, sbase);
+        break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_lut_buckets(const LutRec* luts, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(group_lut_bucket_kernel, dim3(dev::kLutBuckets / 256, (uint32_t)n), dim3(256), 0, st, luts);
     return hipGetLastError();
 }
 

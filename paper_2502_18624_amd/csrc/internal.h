@@ -71,22 +71,48 @@ struct SampledArgs {
 };
 hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s);
 
-// Batched half-sweep.  One descriptor per replica (64 bytes).
+// Batched half-sweep.  One descriptor per replica (64 bytes).  The work of
+// a launch is a list of tiles of 256 threads; replica i owns the tiles
+// [tile_begin, next replica's tile_begin).  A thread of a tile is one
+// 16-byte column vector (32 four-bit or 128 one-bit cells) of one band of
+// `rows` rows, as in the one-lattice kernels.
 struct GroupDesc {
     uint32_t* plane0;      // the replica's planes (P_1 follows P_0)
     uint32_t L;
     uint32_t rows;         // band rows: even, divides L
-    uint32_t hi0;          // 1 when every accept block index fits 32 bits
     uint32_t t0;           // sweep counter at the start of the call
     uint32_t n;            // sweeps for this replica in this call
     uint32_t k0, k1;       // Philox key (seed)
-    uint32_t T4, T8;       // Ising thresholds
-    uint32_t wg_begin;     // first workgroup of this replica in its launch
-    uint32_t bc;           // index of its Blume-Capel table (96 entries)
+    uint32_t T4, T8;       // Ising thresholds (4-bit Ising)
+    uint32_t tile_begin;   // first tile of this replica in its launch
+    uint32_t model;        // 0: Ising 4-bit, 1: Blume-Capel, 2: Ising 1-bit
+    uint32_t tab;          // Blume-Capel: index of its 96-entry table; 1-bit: index of its LutRec
     uint32_t pad[3];
 };
 static_assert(sizeof(GroupDesc) == 64, "descriptor size");
-hipError_t launch_group_half(int model, int color, const GroupDesc* desc, int count, uint32_t total_wgs,
-                             const uint2* tables, uint32_t s, hipStream_t st);
+
+// Table of a 1-bit replica in the batched path: its bucket table (in the
+// replica's own device buffer, rebuilt per call) and the 16 clamped
+// thresholds with the last index below 2^32.
+struct LutRec {
+    uint2* buckets;
+    uint32_t T[16];
+    uint32_t kmax;
+    uint32_t pad;
+};
+static_assert(sizeof(LutRec) == 80, "1-bit record size");
+
+// Models a batched launch may hold (bit m for model m).  A launch whose mask
+// has one bit runs that model's path only (and its register budget).
+constexpr int kMaskIsing = 1, kMaskBC = 2, kMaskLut = 4;
+
+// One colour of sweep s (+ *sbase when sbase is set) for every replica of
+// the list with s < n; grid workgroups (a multiple of 8) walk the `total`
+// tiles, each XCD's workgroups one contiguous eighth of the list.
+hipError_t launch_group_half(int mask, int color, const GroupDesc* desc, int count, uint32_t total,
+                             uint32_t grid, const uint2* bc_tables, const LutRec* luts, uint32_t s,
+                             const uint32_t* sbase, hipStream_t st);
+// Bucket tables of the 1-bit replicas of a batched call.
+hipError_t launch_group_lut_buckets(const LutRec* luts, int n, hipStream_t st);
 
 }  // namespace mcl

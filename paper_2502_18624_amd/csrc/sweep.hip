@@ -114,33 +114,13 @@ __global__ __launch_bounds__(256) void init1_kernel(uint32_t* __restrict__ plane
         planes[g] = init1_word(g, L, W, init_state, k0, k1);
 }
 
-// Bucket table of the 1-bit mode (one thread per bucket): for the draws u
-// of [lo, hi] = [b 2^20, b 2^20 + 2^20 - 1], klo = max{k <= kmax : T[k] <= lo}
-// and `inner` counts the thresholds in (lo, hi].  The sorted table makes
-// the answer klo below the one inner threshold T[klo + 1] and klo + 1 from
-// it on; with none inside it is klo throughout.
+// Bucket table of the 1-bit mode, one thread per bucket (the entry is
+// lut_bucket_addend of sweep_device.h).
 __global__ __launch_bounds__(256) void lut_bucket_kernel(LutTable tab, uint2* __restrict__ out)
 {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= (uint32_t)dev::kLutBuckets) return;
-    const uint32_t lo = b << 20, hi = lo + 0xFFFFFu;
-    uint32_t klo = 0, inner = 0;
-    for (uint32_t k = 1; k < 16; ++k) {
-        if (k > tab.kmax) break;
-        if (tab.T[k] <= lo) klo = k;
-        else if (tab.T[k] <= hi) ++inner;
-    }
-    // the answer is kw + [u >= Tn] on the bucket; stored as kw 2^32 + 2^32 - Tn
-    uint64_t A;
-    if (inner == 1 || (inner == 0 && klo < tab.kmax)) {
-        A = ((uint64_t)klo << 32) + (uint64_t(1) << 32) - tab.T[klo + 1];   // next threshold
-    } else if (inner == 0 && hi != 0xFFFFFFFFu) {
-        A = ((uint64_t)klo << 32) + 1u;               // Tn = 2^32 - 1, above every draw of the bucket
-    } else if (inner == 0 && klo >= 1) {
-        A = (uint64_t)klo << 32;                      // kw = klo - 1, Tn = 0
-    } else {
-        A = uint64_t(1) << 63;                        // exact search
-    }
+    const uint64_t A = dev::lut_bucket_addend(tab.T, tab.kmax, b);
     out[b] = make_uint2((uint32_t)A, (uint32_t)(A >> 32));
 }
 

@@ -342,6 +342,28 @@ __device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t s
 // with any such draw takes the exact search instead.
 constexpr int kLutBuckets = 4096;
 
+// Entry of bucket b: for the draws u of [lo, hi] = [b 2^20, b 2^20 + 2^20 - 1],
+// klo = max{k <= kmax : T[k] <= lo} and `inner` counts the thresholds in
+// (lo, hi].  The sorted table makes the answer klo below the one inner
+// threshold T[klo + 1] and klo + 1 from it on; with none inside it is klo
+// throughout.
+__device__ __forceinline__ uint64_t lut_bucket_addend(const uint32_t* T, uint32_t kmax, uint32_t b)
+{
+    const uint32_t lo = b << 20, hi = lo + 0xFFFFFu;
+    uint32_t klo = 0, inner = 0;
+    for (uint32_t k = 1; k < 16; ++k) {
+        if (k > kmax) break;
+        if (T[k] <= lo) klo = k;
+        else if (T[k] <= hi) ++inner;
+    }
+    // the answer is kw + [u >= Tn] on the bucket; stored as kw 2^32 + 2^32 - Tn
+    if (inner == 1 || (inner == 0 && klo < kmax))
+        return ((uint64_t)klo << 32) + (uint64_t(1) << 32) - T[klo + 1];    // next threshold
+    if (inner == 0 && hi != 0xFFFFFFFFu) return ((uint64_t)klo << 32) + 1u;   // Tn = 2^32 - 1, above the bucket
+    if (inner == 0 && klo >= 1) return (uint64_t)klo << 32;                     // kw = klo - 1, Tn = 0
+    return uint64_t(1) << 63;                                                   // exact search
+}
+
 template <int HM>
 __device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
                                                   uint32_t hu, const uint2* __restrict__ B,

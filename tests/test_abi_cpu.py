@@ -149,11 +149,18 @@ def test_group_tuning_roundtrip_and_validation(mcl):
     t.rows_log2L[10] = 12                     # not a supported band height
     assert lib.mcl_group_tuning_set(ctypes.byref(t)) == -9
     t.rows_log2L[10] = 64
-    t.use_graph = 1
+    for field, bad in (("wg_per_cu", -1), ("wg_per_cu", 33), ("split_models", 2), ("graph_sweeps", 0),
+                       ("graph_sweeps", 65), ("use_graph", 2), ("largest_first", -1)):
+        good = getattr(t, field)
+        setattr(t, field, bad)
+        assert lib.mcl_group_tuning_set(ctypes.byref(t)) == -9, field
+        setattr(t, field, good)
+    t.use_graph, t.wg_per_cu, t.split_models, t.graph_sweeps = 1, 4, 1, 16
     assert lib.mcl_group_tuning_set(ctypes.byref(t)) == 0
     back = GroupTuning()
     lib.mcl_group_tuning_get(ctypes.byref(back))
     assert back.rows_log2L[10] == 64 and back.use_graph == 1
+    assert (back.wg_per_cu, back.split_models, back.graph_sweeps) == (4, 1, 16)
     assert lib.mcl_group_tuning_set(ctypes.byref(saved)) == 0
     assert lib.group_sweep(None, 0, None, None, None) == 0     # empty group is a no-op
 

@@ -181,8 +181,10 @@ def test_measure_ordered_states(mcl):
 
 
 def test_group_sweep_with_one_bit_replicas(mcl):
-    """Mixed groups: the 1-bit replicas advance through the plain path, the
-    others through the batched kernels; all equal the oracle."""
+    """Mixed groups: 1-bit replicas (each with its own bucket table, built by
+    the call) advance in the same batched launches as the 4-bit ones; all
+    equal the oracle, including a 1-bit temperature whose table needs the
+    exact search."""
     rng = np.random.default_rng(11)
     specs = []
     for i in range(6):
@@ -190,6 +192,8 @@ def test_group_sweep_with_one_bit_replicas(mcl):
         L = int(rng.choice([256, 512]))
         specs.append((model, L, 5000 + i, int(rng.integers(1, 5)), float(rng.uniform(0.5, 1.5)) * BETA_C,
                       float(rng.choice([0.0, 1.0]))))
+    specs.append((LUT, 256, 5100, 3, 2.0, 0.0))             # many buckets hold several thresholds
+    specs.append((LUT, 512, 5101, 2, float("inf"), 0.0))
     lats = [mcl.Lattice(m, L, s) for (m, L, s, _, _, _) in specs]
     mcl.group_sweep(lats, [sp[3] for sp in specs], [sp[4] for sp in specs], [sp[5] for sp in specs])
     for lat, (m, L, s, n, b, D) in zip(lats, specs):

@@ -159,7 +159,7 @@ def test_measure_structured_states(mcl):
         assert np.array_equal(m["Cx"], abs(val) * m["nsrc"]) and np.array_equal(m["Cy"], abs(val) * m["nsrc"])
 
 
-def _tuning(mcl, rows=None, graph=0, largest=1):
+def _tuning(mcl, rows=None, graph=0, largest=1, wg=0, split=0, gsweeps=32):
     from paper_2502_18624_amd._lib import GroupTuning
     import ctypes
     t = GroupTuning()
@@ -169,35 +169,41 @@ def _tuning(mcl, rows=None, graph=0, largest=1):
             t.rows_log2L[k] = rows
     t.use_graph = graph
     t.largest_first = largest
+    t.wg_per_cu = wg
+    t.split_models = split
+    t.graph_sweeps = gsweeps
     assert mcl.lib().mcl_group_tuning_set(ctypes.byref(t)) == 0
     return t
 
 
-@pytest.mark.parametrize("rows,graph,largest", [(8, 0, 1), (16, 1, 0), (32, 1, 1), (64, 0, 0)])
-def test_group_sweep_tunings_are_bit_identical(mcl, rows, graph, largest):
+@pytest.mark.parametrize("rows,graph,largest,wg,split,gsweeps", [
+    (8, 0, 1, 0, 0, 32), (16, 1, 0, 2, 1, 2), (32, 1, 1, 1, 0, 3), (64, 0, 0, 8, 1, 32), (16, 1, 1, 4, 0, 1)])
+def test_group_sweep_tunings_are_bit_identical(mcl, rows, graph, largest, wg, split, gsweeps):
     """Every tuning of the batched path gives the plain path's lattices: the
-    draws are keyed by the logical site, never by the launch shape."""
-    print("group tuning", rows, graph, largest, flush=True)
+    draws are keyed by the logical site, never by the launch shape.  The
+    group mixes all three models; three calls of the same shape run plain,
+    then capture a graph, then replay it (graph tunings)."""
+    print("group tuning", rows, graph, largest, wg, split, gsweeps, flush=True)
     import ctypes
     from paper_2502_18624_amd._lib import GroupTuning
     saved = GroupTuning()
     mcl.lib().mcl_group_tuning_get(ctypes.byref(saved))
     try:
-        _tuning(mcl, rows, graph, largest)
-        rng = np.random.default_rng(rows + 10 * graph + 100 * largest)
+        _tuning(mcl, rows, graph, largest, wg, split, gsweeps)
+        rng = np.random.default_rng(rows + 10 * graph + 100 * largest + 1000 * wg)
         specs = []
-        for i in range(7):
-            model = int(rng.integers(0, 2))
-            L = int(rng.choice([64, 128, 192, 256, 512]))
+        for i in range(9):
+            model = int(rng.integers(0, 3))
+            L = int(rng.choice([256, 512, 768] if model == 2 else [64, 128, 192, 256, 512]))
             n = int(rng.integers(0, 5))                     # n = 0: left untouched
             specs.append((model, L, 3000 + i, n, float(rng.uniform(0.5, 1.5)) * BETA_C,
                           float(rng.choice([0.0, 0.5, 1.0]))))
         lats = [mcl.Lattice(m, L, sd) for (m, L, sd, _, _, _) in specs]
-        for rep in range(2):                                 # second call reuses a cached graph
+        for rep in range(3):                                 # plain, capture, replay
             mcl.group_sweep(lats, [sp[3] for sp in specs], [sp[4] for sp in specs], [sp[5] for sp in specs])
         for lat, (m, L, sd, n, b, D) in zip(lats, specs):
-            assert lat.t == 2 * n
-            want = _oracle_run(m, L, sd, 0, 2 * n, b, D)
+            assert lat.t == 3 * n
+            want = _oracle_run(m, L, sd, 0, 3 * n, b, D)
             assert np.array_equal(lat.read(), want), (m, L, n)
     finally:
         mcl.lib().mcl_group_tuning_set(ctypes.byref(saved))
@@ -263,6 +269,26 @@ def test_sampled_x_correlation_in_residue_passes(mcl, monkeypatch, budget, model
     m = lat.measure(mcl.CORR_PROTOCOL)
     Cx, Cy, ns = oracle.corr(s, oracle.CORR_PROTOCOL, m["r"])
     assert np.array_equal(m["Cx"], Cx) and np.array_equal(m["Cy"], Cy)
+
+
+def test_free_waits_for_the_lattice_stream(mcl):
+    """A lattice whose buffer was allocated on the current stream but whose
+    sweeps run on a side stream, freed right after queuing them: the buffer
+    goes back to the caching allocator only once the sweeps have run, so a
+    tensor allocated and filled at once keeps its values."""
+    import torch
+    print("free waits for the stream", flush=True)
+    side = torch.cuda.Stream()
+    for L in (8192, 2048):                   # plain launches; graph replays (L <= 4096, 32-sweep chunks)
+        lat = mcl.Lattice(0, L, 91, stream=side)
+        nbytes = lat.mem.numel()
+        torch.cuda.synchronize()
+        lat.sweep(64, BETA_C)
+        lat.free()
+        x = torch.full((nbytes,), 7, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        assert int((x != 7).sum()) == 0, L
+        del x
 
 
 def test_lattices_on_separate_streams(mcl):
