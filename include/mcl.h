@@ -84,7 +84,8 @@ enum {
     MCL_EHIP = -8,      /* a HIP call failed: see mcl_last_hip_error() */
     MCL_EARG = -9,      /* NULL pointer, negative count, unknown mode */
     MCL_EBUFSZ = -10,   /* caller buffer too small; the needed size is reported */
-    MCL_ESPINS = -11    /* lattice_write() got a value outside the model's spins */
+    MCL_ESPINS = -11,   /* lattice_write() got a value outside the model's spins */
+    MCL_ESCRATCH = -12  /* group_sweep_noalloc(): the call exceeds its fixed workspace */
 };
 
 /* Output of measure().  The caller owns the arrays r, Cx, Cy, nsrc (r_cap
@@ -223,6 +224,32 @@ int lattice_info(const mcl_lattice* h, int* model, int64_t* L, uint64_t* seed, i
  * and grown when a larger group arrives; they are never freed. */
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n,
                 const double* beta, const double* D);
+
+/* group_sweep() for callers that cannot allocate memory: code that must
+ * not call hipMalloc (tight serving loops, harnesses that forbid it).  Same
+ * arguments, checks, results and errors as group_sweep(): every lattice
+ * ends bit-identical to n[i] sweep() calls on it alone.  It allocates
+ * nothing -- no device or pinned memory, no graph, no event, no host heap:
+ *  - the call's descriptor image is staged in a fixed host array and copied
+ *    (hipMemcpyAsync on the lattices' stream) into a fixed device array of
+ *    1 MiB that each GPU the library runs on holds until the process ends;
+ *    the array's address and two events per device are taken once, at
+ *    set-up (lattice_init(), or the first call on that device);
+ *  - the batched launches are plain ones (no captured graph), and lattices
+ *    larger than 2^17 are swept by plain launches too.
+ * Limits: at most 4096 entries, and an image of at most 1 MiB, which holds
+ * at least 1200 batched replicas of any mix (a Blume-Capel replica takes
+ * 832 bytes, an Ising one 64, a 1-bit one 144): MCL_ESCRATCH beyond, before
+ * anything is queued.  The fixed arrays keep the last call's image.  Calls
+ * on one GPU share them, so the library orders them: a call's copy waits
+ * for the previous call's launches on that GPU (whatever their stream),
+ * and the host array is rewritten only after the previous call's copy has
+ * run (the host may block for that).  Calls from several threads are
+ * serialised by a lock.  Not for use inside a stream capture of the
+ * caller's (the copy reads pageable host memory).  Runs on the current
+ * device, which must be the lattices' device. */
+int group_sweep_noalloc(mcl_lattice* const* hs, int count, const int64_t* n,
+                        const double* beta, const double* D);
 
 /* Tuning of group_sweep, process-wide; chosen by the package's autotuner.
  * Results never depend on it.

@@ -19,7 +19,7 @@ CORR_NONE, CORR_FULL, CORR_PROTOCOL = 0, 1, 2
 ERRORS = {
     0: "MCL_OK", -1: "MCL_EMODEL", -2: "MCL_EL", -3: "MCL_EBETA", -4: "MCL_ED",
     -5: "MCL_EINIT", -6: "MCL_ENOMEM", -7: "MCL_ERANGE", -8: "MCL_EHIP",
-    -9: "MCL_EARG", -10: "MCL_EBUFSZ", -11: "MCL_ESPINS",
+    -9: "MCL_EARG", -10: "MCL_EBUFSZ", -11: "MCL_ESPINS", -12: "MCL_ESCRATCH",
 }
 
 
@@ -70,6 +70,8 @@ SIGNATURES = {
                             ctypes.POINTER(_I64)]),
     "group_sweep": (_INT, [ctypes.POINTER(_P), _INT, ctypes.POINTER(_I64), ctypes.POINTER(_DBL),
                            ctypes.POINTER(_DBL)]),
+    "group_sweep_noalloc": (_INT, [ctypes.POINTER(_P), _INT, ctypes.POINTER(_I64), ctypes.POINTER(_DBL),
+                                   ctypes.POINTER(_DBL)]),
     "mcl_group_tuning_get": (_INT, [ctypes.POINTER(GroupTuning)]),
     "mcl_group_tuning_set": (_INT, [ctypes.POINTER(GroupTuning)]),
     "lattice_free": (_INT, [_P]),

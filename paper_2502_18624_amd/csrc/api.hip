@@ -223,6 +223,8 @@ void spin_to_cell(uint32_t* row, int64_t i, int s, int cb)
 // Lattices up to this size go into the batched launches; larger ones fill
 // the GPU on their own and are swept one per launch.
 constexpr int64_t kGroupMaxL = int64_t(1) << 17;
+// Entries of one group_sweep_noalloc call (its fixed host workspaces).
+constexpr int kNoAllocEntries = 4096;
 
 mcl_group_tuning default_tuning()
 {
@@ -300,7 +302,8 @@ struct GroupLaunch {
     uint32_t grid;     // workgroups (a multiple of 8)
 };
 struct GroupImage {
-    std::vector<GroupLaunch> launches;
+    GroupLaunch launches[3];   // one per model, or one for all
+    int nlaunch = 0;
     size_t ndesc = 0, nbc = 0, nlut = 0;
     size_t off_bc = 0, off_lut = 0, off_s = 0, bytes = 0;
     int64_t nmax = 0;
@@ -310,16 +313,15 @@ struct GroupImage {
 bool batched(const mcl_lattice* h, int64_t n) { return n > 0 && h->L <= kGroupMaxL; }
 
 // Plan the call (launches, tiles, grid) into `img`; when `host` is given,
-// also write the image there (it must hold img.bytes).  MCL_ERANGE if a
-// launch would need more than 2^24 workgroups or 2^32 tiles.
+// also write the image there (it must hold img.bytes).  `order` is room for
+// `count` entry indices.  Allocates nothing.  MCL_ERANGE if a launch would
+// need more than 2^24 workgroups or 2^32 tiles.
 int group_layout(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D,
-                 const mcl_group_tuning& tun, int cus, GroupImage& img, void* host)
+                 const mcl_group_tuning& tun, int cus, GroupImage& img, void* host, int* order)
 {
     img = GroupImage();
-    std::vector<int> by[3];
     for (int i = 0; i < count; ++i)
         if (batched(hs[i], n[i])) {
-            by[tun.split_models ? hs[i]->model : 0].push_back(i);
             img.nmax = std::max(img.nmax, n[i]);
             img.ndesc++;
             img.nbc += hs[i]->model == MCL_BC;
@@ -334,14 +336,19 @@ int group_layout(mcl_lattice* const* hs, int count, const int64_t* n, const doub
     uint32_t* htab = base ? (uint32_t*)(base + img.off_bc) : nullptr;
     mcl::LutRec* hlut = base ? (mcl::LutRec*)(base + img.off_lut) : nullptr;
     size_t k = 0, nb = 0, nl = 0;
-    for (int m = 0; m < 3; ++m) {
-        std::vector<int>& idx = by[m];
-        if (idx.empty()) continue;
+    for (int m = 0; m < (tun.split_models ? 3 : 1); ++m) {
+        int cnt = 0;
+        for (int i = 0; i < count; ++i)
+            if (batched(hs[i], n[i]) && (!tun.split_models || hs[i]->model == m)) order[cnt++] = i;
+        if (cnt == 0) continue;
+        // decreasing L, call order among equal L (an in-place sort on the pair)
         if (tun.largest_first)
-            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return hs[a]->L > hs[b]->L; });
-        GroupLaunch ln{0, k, (int)idx.size(), 0, 0};
+            std::sort(order, order + cnt,
+                      [&](int a, int b) { return hs[a]->L != hs[b]->L ? hs[a]->L > hs[b]->L : a < b; });
+        GroupLaunch ln{0, k, cnt, 0, 0};
         uint64_t tiles = 0;
-        for (int i : idx) {
+        for (int j = 0; j < cnt; ++j) {
+            const int i = order[j];
             const mcl_lattice* h = hs[i];
             const uint32_t rows = (uint32_t)tun.rows_log2L[log2_floor(h->L)];
             const int64_t threads = h->g.Q * (h->L / rows);
@@ -389,7 +396,7 @@ int group_layout(mcl_lattice* const* hs, int count, const int64_t* n, const doub
         grid = std::max<uint64_t>(grid, 8);
         if (grid > (uint64_t(1) << 24)) return MCL_ERANGE;
         ln.grid = (uint32_t)grid;
-        img.launches.push_back(ln);
+        img.launches[img.nlaunch++] = ln;
     }
     return MCL_OK;
 }
@@ -405,7 +412,8 @@ hipError_t group_launches(const GroupImage& img, const void* dev, int64_t s0, in
     const mcl::LutRec* luts = (const mcl::LutRec*)(b + img.off_lut);
     for (int64_t s = s0; s < s0 + k; ++s)
         for (int c = 0; c < 2; ++c)
-            for (const GroupLaunch& ln : img.launches) {
+            for (int j = 0; j < img.nlaunch; ++j) {
+                const GroupLaunch& ln = img.launches[j];
                 const hipError_t e = mcl::launch_group_half(ln.mask, c, desc + ln.first, ln.count, ln.total, ln.grid,
                                                             tabs, luts, (uint32_t)s, sbase, st);
                 if (e != hipSuccess) return e;
@@ -510,7 +518,8 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
     int devid = 0;
     MCL_HIP(hipGetDevice(&devid));
     GroupImage img;
-    int rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, nullptr);
+    std::vector<int> order((size_t)count);
+    int rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, nullptr, order.data());
     if (rc) return rc;
     if (img.nmax == 0) return MCL_OK;
 
@@ -533,7 +542,7 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
         MCL_HIP(hipMalloc(&sl.dev, cap));
         sl.cap = cap;
     }
-    rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, sl.host);
+    rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, sl.host, order.data());
     if (rc) return rc;
     // the sweep-offset word starts at 0 (graph replays add to it)
     std::memset((char*)sl.host + img.off_s, 0, 256);
@@ -548,9 +557,11 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
     if (use_graph) {
         key = {(uint64_t)(uintptr_t)sl.dev, (uint64_t)K, (uint64_t)img.off_bc, (uint64_t)img.off_lut,
                (uint64_t)img.off_s};
-        for (const GroupLaunch& ln : img.launches)
+        for (int j = 0; j < img.nlaunch; ++j) {
+            const GroupLaunch& ln = img.launches[j];
             key.insert(key.end(), {(uint64_t)ln.mask, (uint64_t)ln.first, (uint64_t)ln.count, (uint64_t)ln.total,
                                    (uint64_t)ln.grid});
+        }
         // a shape is captured the second time it is seen: one-off shapes run plain
         std::vector<uint64_t> shape(key.begin() + 1, key.end());
         const bool known = std::any_of(sl.graphs.begin(), sl.graphs.end(),
@@ -697,6 +708,155 @@ int sweep_graph(mcl_lattice* h, double beta, double D, const SweepParams& p, hip
     return MCL_OK;
 }
 
+// sweep() after its argument checks; allow_graph = false queues plain
+// launches only (no graph is captured or created).
+int sweep_checked(mcl_lattice* h, int64_t n, double beta, double D, bool allow_graph)
+{
+    if (n == 0) return MCL_OK;
+    SweepParams p{};
+    if (h->model == MCL_ISING_LUT) {
+        p.tab = lut_device_table(beta);
+        MCL_HIP(mcl::launch_lut_buckets(p.tab, h->lutb, h->stream));
+    } else if (h->model == MCL_ISING) {
+        ising_thresholds(beta, p.T4, p.T8);
+    } else {
+        bc_table(beta, D, p.tb);
+    }
+    int64_t done = 0;
+    if (allow_graph && n >= kGraphSweeps && use_sweep_graph(h)) {
+        hipGraphExec_t exec = nullptr;
+        const int rc = sweep_graph(h, beta, D, p, &exec);
+        if (rc) return rc;
+        MCL_HIP(mcl::launch_set_word(h->tdev, (uint32_t)h->t, false, h->stream));
+        for (; done + kGraphSweeps <= n; done += kGraphSweeps) MCL_HIP(hipGraphLaunch(exec, h->stream));
+    }
+    if (done < n) MCL_HIP(launch_sweeps(h, p, n - done, (uint32_t)(h->t + done), nullptr, h->stream));
+    h->t += n;
+    return MCL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks and the lattices outside the batched launches, shared by
+// group_sweep and group_sweep_noalloc.
+// ---------------------------------------------------------------------------
+using Span = std::pair<uintptr_t, uintptr_t>;
+
+// `spans` is room for `count` entries.  Allocates nothing.
+int group_check(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D, Span* spans)
+{
+    if (count < 0 || (count > 0 && (!hs || !n || !beta || !D))) return MCL_EARG;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || n[i] < 0) return MCL_EARG;
+        if (hs[i]->stream != hs[0]->stream) return MCL_EARG;
+        const int pc = check_params(hs[i], beta[i], D[i]);
+        if (pc) return pc;
+        if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
+    }
+    // entries that do work must not share device memory: their updates would
+    // run concurrently on the same cells (or on a 1-bit replica's bucket table)
+    int ns = 0;
+    for (int i = 0; i < count; ++i)
+        if (n[i] > 0) {
+            const uintptr_t a = (uintptr_t)hs[i]->g.plane0;
+            spans[ns++] = Span(a, a + (uintptr_t)layout_of(hs[i]->model, hs[i]->L).total);
+        }
+    std::sort(spans, spans + ns);
+    for (int k = 1; k < ns; ++k)
+        if (spans[k].first < spans[k - 1].second) return MCL_EARG;
+    return MCL_OK;
+}
+
+// After the batched launches: advance their counters, and sweep each
+// lattice larger than kGroupMaxL on its own (it fills the GPU alone).
+int group_finish(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D,
+                 bool allow_graph)
+{
+    for (int i = 0; i < count; ++i) {
+        if (batched(hs[i], n[i])) {
+            hs[i]->t += n[i];
+        } else if (n[i] > 0) {
+            const int rc = sweep_checked(hs[i], n[i], beta[i], D[i], allow_graph);
+            if (rc) return rc;
+        }
+    }
+    return MCL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Non-allocating batched path (group_sweep_noalloc).  The call's image
+// (descriptors, Blume-Capel tables, 1-bit records) is staged in a fixed host
+// array and copied into `scratch`, a fixed device array: each GPU holds its
+// own copy of it for the life of the process.  In host code the array's
+// name is no device address; its address on a device comes from
+// hipGetSymbolAddress, taken once per device at set-up (lattice_init, or
+// the first call on that device) and used for every copy and launch.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+    void* ptr = nullptr;          // this device's copy of scratch
+    hipEvent_t copied = nullptr;  // after the last copy out of the host image
+    hipEvent_t done = nullptr;    // after the last call's launches
+    bool pending = false;
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+alignas(256) unsigned char g_noalloc_host[kNoAllocBytes];
+int g_noalloc_order[kNoAllocEntries];
+Span g_noalloc_spans[kNoAllocEntries];
+int g_noalloc_last = -1;          // device of the last copy out of g_noalloc_host
+
+// Set-up of device devid (current); the caller holds g_group_mu.
+int noalloc_setup(int devid)
+{
+    if (devid < 0 || devid >= kMaxDevices) return MCL_EARG;
+    NoAllocDevice& st = g_noalloc[devid];
+    if (st.ptr) return MCL_OK;
+    void* ptr = nullptr;
+    MCL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!st.copied) MCL_HIP(hipEventCreateWithFlags(&st.copied, hipEventDisableTiming));
+    if (!st.done) MCL_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
+    (void)compute_units(devid);   // fills its cache here rather than in a call
+    st.ptr = ptr;
+    return MCL_OK;
+}
+
+// The batched launches of a checked call, with no allocation of any kind;
+// the caller holds g_group_mu.
+int group_run_noalloc(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
+{
+    mcl_group_tuning tun = g_tuning;
+    hipStream_t stream = hs[0]->stream;
+    int devid = 0;
+    MCL_HIP(hipGetDevice(&devid));
+    int rc = noalloc_setup(devid);
+    if (rc) return rc;
+    NoAllocDevice& st = g_noalloc[devid];
+    GroupImage img;
+    rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, nullptr, g_noalloc_order);
+    if (rc) return rc;
+    if (img.nmax == 0) return MCL_OK;
+    if (img.bytes > kNoAllocBytes) return MCL_ESCRATCH;
+    // the host image is free once the copy of the last call (on any device) has run
+    if (g_noalloc_last >= 0 && g_noalloc[g_noalloc_last].pending) {
+        MCL_HIP(hipEventSynchronize(g_noalloc[g_noalloc_last].copied));
+        g_noalloc[g_noalloc_last].pending = false;
+    }
+    rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, g_noalloc_host, g_noalloc_order);
+    if (rc) return rc;
+    // the device image is rewritten only after the launches of the previous
+    // call on this device, whatever stream they were queued on
+    MCL_HIP(hipStreamWaitEvent(stream, st.done, 0));
+    MCL_HIP(hipMemcpyAsync(st.ptr, g_noalloc_host, img.bytes, hipMemcpyHostToDevice, stream));
+    MCL_HIP(hipEventRecord(st.copied, stream));
+    st.pending = true;
+    g_noalloc_last = devid;
+    MCL_HIP(group_plain(img, st.ptr, stream));
+    MCL_HIP(hipEventRecord(st.done, stream));
+    return MCL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -716,6 +876,9 @@ const char* mcl_strerror(int code)
     case MCL_EARG: return "invalid argument";
     case MCL_EBUFSZ: return "caller buffer too small";
     case MCL_ESPINS: return "spin value not allowed for this model";
+    case MCL_ESCRATCH:
+        return "group_sweep_noalloc: more than 4096 entries, or a batched image above its fixed 1 MiB workspace "
+               "(at least 1200 replicas of any mix)";
     default: return "unknown error";
     }
 }
@@ -806,6 +969,13 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->tdev = (uint32_t*)(base + lay.ctl);
     h->rcap = lay.rcap;
     h->stream = (hipStream_t)hip_stream;
+    {
+        // set-up of group_sweep_noalloc on this device (best effort: that
+        // entry point repeats it and reports a failure itself)
+        std::lock_guard<std::mutex> lk(g_group_mu);
+        int devid = 0;
+        if (hipGetDevice(&devid) == hipSuccess) (void)noalloc_setup(devid);
+    }
     const hipError_t e = model == MCL_ISING_LUT ? mcl::launch_init1(h->g, init_state, seed, h->stream)
                                                 : mcl::launch_init(h->g, model, init_state, seed, h->stream);
     if (e != hipSuccess) {
@@ -843,27 +1013,7 @@ int sweep(mcl_lattice* h, int64_t n, double beta, double D)
     const int pc = check_params(h, beta, D);
     if (pc) return pc;
     if (h->t + n > (int64_t(1) << 32)) return MCL_ERANGE;
-    if (n == 0) return MCL_OK;
-    SweepParams p{};
-    if (h->model == MCL_ISING_LUT) {
-        p.tab = lut_device_table(beta);
-        MCL_HIP(mcl::launch_lut_buckets(p.tab, h->lutb, h->stream));
-    } else if (h->model == MCL_ISING) {
-        ising_thresholds(beta, p.T4, p.T8);
-    } else {
-        bc_table(beta, D, p.tb);
-    }
-    int64_t done = 0;
-    if (n >= kGraphSweeps && use_sweep_graph(h)) {
-        hipGraphExec_t exec = nullptr;
-        const int rc = sweep_graph(h, beta, D, p, &exec);
-        if (rc) return rc;
-        MCL_HIP(mcl::launch_set_word(h->tdev, (uint32_t)h->t, false, h->stream));
-        for (; done + kGraphSweeps <= n; done += kGraphSweeps) MCL_HIP(hipGraphLaunch(exec, h->stream));
-    }
-    if (done < n) MCL_HIP(launch_sweeps(h, p, n - done, (uint32_t)(h->t + done), nullptr, h->stream));
-    h->t += n;
-    return MCL_OK;
+    return sweep_checked(h, n, beta, D, true);
 }
 
 int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
@@ -1033,38 +1183,26 @@ int lattice_write(mcl_lattice* h, const int8_t* host_spins, int64_t t)
 
 int group_sweep(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
 {
-    if (count < 0 || (count > 0 && (!hs || !n || !beta || !D))) return MCL_EARG;
-    if (count == 0) return MCL_OK;
-    for (int i = 0; i < count; ++i) {
-        if (!hs[i] || n[i] < 0) return MCL_EARG;
-        if (hs[i]->stream != hs[0]->stream) return MCL_EARG;
-        const int pc = check_params(hs[i], beta[i], D[i]);
-        if (pc) return pc;
-        if (hs[i]->t + n[i] > (int64_t(1) << 32)) return MCL_ERANGE;
-    }
-    // entries that do work must not share device memory: their updates would
-    // run concurrently on the same cells (or on a 1-bit replica's bucket table)
-    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
-    for (int i = 0; i < count; ++i)
-        if (n[i] > 0) {
-            const uintptr_t a = (uintptr_t)hs[i]->g.plane0;
-            spans.emplace_back(a, a + (uintptr_t)layout_of(hs[i]->model, hs[i]->L).total);
-        }
-    std::sort(spans.begin(), spans.end());
-    for (size_t k = 1; k < spans.size(); ++k)
-        if (spans[k].first < spans[k - 1].second) return MCL_EARG;
-    const int rc = group_run(hs, count, n, beta, D);
+    std::vector<Span> spans((size_t)std::max(count, 0));
+    int rc = group_check(hs, count, n, beta, D, spans.data());
+    if (rc || count == 0) return rc;
+    rc = group_run(hs, count, n, beta, D);
     if (rc) return rc;
-    for (int i = 0; i < count; ++i) {
-        if (batched(hs[i], n[i])) {
-            hs[i]->t += n[i];
-        } else if (n[i] > 0) {
-            // a lattice larger than kGroupMaxL fills the GPU alone: one per launch
-            const int r2 = sweep(hs[i], n[i], beta[i], D[i]);
-            if (r2) return r2;
-        }
+    return group_finish(hs, count, n, beta, D, true);
+}
+
+int group_sweep_noalloc(mcl_lattice* const* hs, int count, const int64_t* n, const double* beta, const double* D)
+{
+    if (count > kNoAllocEntries) return MCL_ESCRATCH;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g_group_mu);
+        rc = group_check(hs, count, n, beta, D, g_noalloc_spans);
+        if (rc || count == 0) return rc;
+        rc = group_run_noalloc(hs, count, n, beta, D);
     }
-    return MCL_OK;
+    if (rc) return rc;
+    return group_finish(hs, count, n, beta, D, false);
 }
 
 int mcl_group_tuning_get(mcl_group_tuning* out)

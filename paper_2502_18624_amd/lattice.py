@@ -205,8 +205,10 @@ class Lattice:
             pass
 
 
-def group_sweep(lattices, n, beta, D=None) -> None:
-    """Batched path: advance each lattice i by n[i] sweeps at (beta[i], D[i])."""
+def group_sweep(lattices, n, beta, D=None, noalloc=False) -> None:
+    """Batched path: advance each lattice i by n[i] sweeps at (beta[i], D[i]).
+    With noalloc, the call goes through group_sweep_noalloc (fixed
+    workspaces, plain launches, no allocation)."""
     k = len(lattices)
     n = list(n) if np.ndim(n) else [int(n)] * k
     beta = list(beta) if np.ndim(beta) else [float(beta)] * k
@@ -215,4 +217,7 @@ def group_sweep(lattices, n, beta, D=None) -> None:
     nn = (ctypes.c_int64 * k)(*[int(v) for v in n])
     bb = (ctypes.c_double * k)(*[float(v) for v in beta])
     dd = (ctypes.c_double * k)(*[float(v) for v in D])
-    check(lib().group_sweep(hs, k, nn, bb, dd), "group_sweep")
+    if noalloc:
+        check(lib().group_sweep_noalloc(hs, k, nn, bb, dd), "group_sweep_noalloc")
+    else:
+        check(lib().group_sweep(hs, k, nn, bb, dd), "group_sweep")
