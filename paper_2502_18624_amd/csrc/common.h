@@ -63,6 +63,66 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     return Philox4{c0, c1, c2, c3};
 }
 
+// The same with the first round's product M0 * c0 given (a caller whose
+// counters differ by a constant k can pass M0 * c + M0 * k, one multiply-add
+// with a constant addend, instead of adding k to the counter first).
+__device__ __forceinline__ Philox4 philox4x32_10_p0(uint64_t p0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                    uint32_t k1)
+{
+    uint32_t c0;
+    {
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+#pragma unroll
+    for (int r = 1; r < 10; ++r) {
+        const uint64_t q0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t q1 = (uint64_t)kPhiloxM1 * c2;
+        uint32_t n0, n2;
+        if (r < 2) {
+            n0 = (uint32_t)(q1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(q0 >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3((uint32_t)(q1 >> 32), c1, k0);
+            n2 = xor3((uint32_t)(q0 >> 32), c3, k1);
+        }
+        c1 = (uint32_t)q1;
+        c3 = (uint32_t)q0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+// M0 * c + a (64-bit) in one v_mad_u64_u32, with the constant addend a in
+// scalar registers and M0 in a vector register (a VOP3 reads one scalar
+// operand; left to itself the compiler keeps M0 scalar and copies each
+// addend into vector registers on every use).
+__device__ __forceinline__ uint64_t mad_m0(uint32_t c, uint64_t a)
+{
+    uint64_t d;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(d) : "v"(c), "v"(kPhiloxM0), "s"(a) : "vcc");
+    return d;
+}
+
+// (a ^ b) + c in one VALU instruction (v_xad_u32).  Written out, a chain of
+// these is re-associated into separate xors and three-input adds.
+__device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t philox_word(const Philox4& p, int i)
 {
     return i == 0 ? p.v0 : i == 1 ? p.v1 : i == 2 ? p.v2 : p.v3;

@@ -51,13 +51,22 @@ __device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t
                                              uint32_t hu, uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
 {
     uint32_t a4 = 0, a8 = 0;
+    // the low counter words of the vector's 8 blocks are lo32(blk0) + k
+    // without a wrap unless the high word varies per lane (HM 2), so the first
+    // round's product M0 (lo32(blk0) + k) is one multiply-add with the
+    // constant M0 k
+    const uint32_t c0 = lo32(blk0);
 #pragma unroll
     for (int h = 1; h >= 0; --h) {
         Philox4 P[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
+            if (HM == 2)
+                P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
+            else
+                P[d] = philox4x32_10_p0(mad_m0(c0, (uint64_t)kPhiloxM0 * (uint32_t)(2 * d + h)), hiw<HM>(b, hu), t,
+                                        color, k0, k1);
         }
 #pragma unroll
         for (int jj = 3; jj >= 0; --jj)
@@ -84,12 +93,25 @@ __device__ __forceinline__ uint32_t horizontal(const uint4& mid, int d, uint32_t
 
 // ---------------------------------------------------------------------------
 // Ising vector update (32 cells).  Cells hold n in {0, 2}; n ^ src is 2
-// for a misaligned neighbour, so half the per-nibble sum of the four xors is
-// the number m of misaligned neighbours.  The flip rule of section 3.2
-// (always with at most two aligned neighbours, with probability e^{-4 beta}
-// with three, e^{-8 beta} with four) is: flip iff m + [u < T4] + [u < T8]
-// >= 2, since T8 <= T4.  Adding 6 moves that test to nibble bit 3.
+// for a misaligned neighbour, so S = 4 + the per-nibble sum of the four
+// xors is 4 + 2 m, m the number of misaligned neighbours (at most 12: no
+// carry between nibbles).  The flip rule of section 3.2 (always with at most
+// two aligned neighbours, with probability e^{-4 beta} with three,
+// e^{-8 beta} with four) reads, with a4 = [u < T4] and a8 = [u < T8], which
+// implies a4 since T8 <= T4:
+//   flip = [m >= 2] | ([m == 1] & a4) | ([m == 0] & a8)
+//        = S.bit3 | (S.bit1 & a4) | a8,
+// since m >= 2 iff S >= 8, and for m < 2 bit 1 of S is [m == 1].  Every
+// term is moved to nibble bit 1, where a flip toggles n (0 <-> 2): bit 3 by
+// a shift of S, and a4 / a8 by shifting the transposed masks so that bit
+// 4j + d (cell j of word d) lands on 4j + 1.
 // ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ uint32_t to_bit1(uint32_t m)
+{
+    return D == 0 ? (m << 1) : (m >> (D - 1));
+}
+
 template <int HM>
 __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
                                            uint32_t halo, bool odd, uint64_t blk0, uint32_t t, uint32_t color,
@@ -102,10 +124,14 @@ __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, co
     for (int d = 0; d < 4; ++d) {
         const uint32_t s = pick(src, d);
         const uint32_t hs = horizontal(mid, d, halo, odd);
-        const uint32_t m = ((pick(up, d) ^ s) + (pick(dn, d) ^ s) + (pick(mid, d) ^ s) + (hs ^ s)) >> 1;
-        const uint32_t lvl = ((m4 >> d) & 0x11111111u) + ((m8 >> d) & 0x11111111u);
-        const uint32_t f = (m + lvl + 0x66666666u) & 0x88888888u;
-        res[d] = s ^ (f >> 2);
+        uint32_t S = xad(pick(up, d), s, 0x44444444u);
+        S = xad(pick(dn, d), s, S);
+        S = xad(pick(mid, d), s, S);
+        S = xad(hs, s, S);
+        const uint32_t a4 = d == 0 ? to_bit1<0>(m4) : d == 1 ? to_bit1<1>(m4) : d == 2 ? to_bit1<2>(m4) : to_bit1<3>(m4);
+        const uint32_t a8 = d == 0 ? to_bit1<0>(m8) : d == 1 ? to_bit1<1>(m8) : d == 2 ? to_bit1<2>(m8) : to_bit1<3>(m8);
+        const uint32_t f = ((S >> 2) | (S & a4) | a8) & 0x22222222u;
+        res[d] = s ^ f;
     }
     return make_uint4(res[0], res[1], res[2], res[3]);
 }
