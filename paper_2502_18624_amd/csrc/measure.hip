@@ -804,7 +804,12 @@ uint32_t sy_chunk()
 
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s)
 {
-    const int64_t rows = pick_rows(g.L, 16);
+    // bands of 16 to 64 rows: as tall as leaves a full persistent grid
+    // (kMaxGrid workgroups of 256 threads) with one task per thread or more;
+    // a band re-reads two halo rows, so taller bands read less
+    int64_t want = 16;
+    while (want < 64 && g.Q * (g.L / (2 * want)) >= (int64_t)kMaxGrid * 256) want *= 2;
+    const int64_t rows = pick_rows(g.L, want);
     const int64_t threads = g.Q * (g.L / rows);
     const uint32_t grid = grid_cap((uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid));
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
