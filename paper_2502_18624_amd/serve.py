@@ -10,8 +10,14 @@ The server:
 - runs ticks: one ``group_sweep`` over all live jobs, each advancing by a
   chunk of sweeps sized so that a tick takes about ``tick_seconds``; jobs
   that arrive meanwhile join at the next tick (continuous batching);
-- retires finished jobs (final measurement, memory freed) and records
-  arrival -> admission -> completion times.
+- keeps up to ``depth`` ticks queued on the device: after queuing a tick it
+  records an event and waits only for the event of the tick ``depth``
+  before, so the host plans and queues the next tick while the device runs
+  the current one (no device-wide synchronisation);
+- retires finished jobs on a worker thread (final measurement, optional
+  digest, memory freed) while the following ticks run; a job's memory
+  returns to the budget when its retirement completes;
+- records arrival -> admission -> completion times.
 
 Because the draws are keyed by (seed, sweep, site), a job's result does not
 depend on which other jobs shared its ticks or how its sweeps were chunked.
@@ -21,6 +27,8 @@ from __future__ import annotations
 import hashlib
 import math
 import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -79,6 +87,20 @@ class LibraryBackend:
         import torch
         torch.cuda.synchronize()
 
+    def record(self):
+        """A timing event queued on the current stream."""
+        import torch
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        return ev
+
+    def wait(self, ev):
+        ev.synchronize()
+
+    def elapsed(self, a, b):
+        """Seconds between two completed events."""
+        return a.elapsed_time(b) * 1e-3
+
     def finish(self, handle, corr):
         return handle.measure(corr)
 
@@ -91,8 +113,12 @@ class LibraryBackend:
 
 class Server:
     def __init__(self, backend=None, hbm_budget=250e9, tick_seconds=0.02, max_chunk=256, clock=time.perf_counter,
-                 rate_guess=2.0e12, keep_digest=True):
+                 rate_guess=2.0e12, keep_digest=True, depth=2, retire_thread=True):
         self.backend = backend or LibraryBackend()
+        self.depth = max(1, int(depth))     # ticks queued on the device at most
+        self._inflight = deque()            # (start event, end event, updates) of queued ticks
+        self._retiring = []                 # (job, future or None) of jobs being retired
+        self._pool = ThreadPoolExecutor(max_workers=1) if retire_thread else None
         self.budget = float(hbm_budget)
         self.tick_seconds = tick_seconds
         self.max_chunk = max_chunk
@@ -141,39 +167,74 @@ class Server:
         return max(1, min(self.max_chunk, c))
 
     def tick(self):
+        """Queue one tick; wait for the tick `depth` before it; hand the jobs
+        this tick completes to the retirement worker."""
         if not self.live:
             return 0
         chunk = self._chunk()
         n = [min(chunk, j.sweeps - j.done) for j in self.live]
-        t_start = self.clock()
+        ev0 = self.backend.record()
         self.backend.group_sweep([j.handle for j in self.live], n, [j.beta for j in self.live],
                                  [j.D for j in self.live])
-        self.backend.synchronize()
-        el = self.clock() - t_start
+        ev1 = self.backend.record()
         upd = sum(k * j.L * j.L for k, j in zip(n, self.live))
-        if el > 0 and upd > 0:
-            self.rate = 0.7 * self.rate + 0.3 * (upd / el)
+        self._inflight.append((ev0, ev1, upd))
         for k, j in zip(n, self.live):
-            j.done += k
+            j.done += k          # queued: later ticks and the final measurement follow in stream order
         self.ticks += 1
         self._retire()
+        while len(self._inflight) > self.depth:
+            self._complete_oldest()
+        self._collect(block=False)
         return upd
+
+    def _complete_oldest(self):
+        ev0, ev1, upd = self._inflight.popleft()
+        self.backend.wait(ev1)
+        el = self.backend.elapsed(ev0, ev1)
+        if el > 0 and upd > 0:
+            self.rate = 0.7 * self.rate + 0.3 * (upd / el)
+
+    def _finish_job(self, j):
+        j.result = self.backend.finish(j.handle, j.corr)      # waits for the job's last tick
+        if self.keep_digest:
+            j.digest = hashlib.sha256(np.asarray(self.backend.packed(j.handle)).tobytes()).hexdigest()
+        j.finished = self.now()
+        self.backend.free(j.handle)
+        j.handle = None
+        return j
 
     def _retire(self):
         still = []
         for j in self.live:
             if j.done >= j.sweeps:
-                j.result = self.backend.finish(j.handle, j.corr)
-                if self.keep_digest:
-                    j.digest = hashlib.sha256(np.asarray(self.backend.packed(j.handle)).tobytes()).hexdigest()
-                j.finished = self.now()
-                self.backend.free(j.handle)
-                j.handle = None
-                self.in_use -= self.backend.footprint(j.model, j.L)
-                self.finished.append(j)
+                if self._pool is None:
+                    self._finish_job(j)
+                    self._retiring.append((j, None))
+                else:
+                    self._retiring.append((j, self._pool.submit(self._finish_job, j)))
             else:
                 still.append(j)
         self.live = still
+
+    def _collect(self, block):
+        """Account the retirements that have completed (all of them if block)."""
+        keep = []
+        for j, fut in self._retiring:
+            if fut is not None and not block and not fut.done():
+                keep.append((j, fut))
+                continue
+            if fut is not None:
+                fut.result()                                  # re-raises a failed retirement
+            self.in_use -= self.backend.footprint(j.model, j.L)
+            self.finished.append(j)
+        self._retiring = keep
+
+    def drain(self):
+        """Wait for every queued tick and retirement."""
+        while self._inflight:
+            self._complete_oldest()
+        self._collect(block=True)
 
     # -- a whole trace -------------------------------------------------------
     def run_trace(self, jobs, stop_after=None):
@@ -183,7 +244,7 @@ class Server:
         if self.t0 is None:
             self.t0 = self.clock()
         i = 0
-        while i < len(arrivals) or self.pending or self.live:
+        while i < len(arrivals) or self.pending or self.live or self._retiring:
             now = self.now()
             while i < len(arrivals) and arrivals[i].arrival <= now:
                 self.submit(arrivals[i])
@@ -193,12 +254,22 @@ class Server:
                 self.tick()
                 if stop_after is not None and self.ticks >= stop_after:
                     break
+            elif self._retiring or self._inflight:
+                # nothing to sweep: let the queued work and retirements finish
+                while self._inflight:
+                    self._complete_oldest()
+                self._collect(block=not self.pending and i >= len(arrivals))
+                if self._retiring:
+                    time.sleep(0.0005)
             elif i < len(arrivals):
                 # idle until the next arrival
                 if hasattr(self.clock, "advance_to"):
                     self.clock.advance_to(self.t0 + arrivals[i].arrival)
                 else:
                     time.sleep(max(0.0, min(arrivals[i].arrival - self.now(), 0.05)))
+            elif self.pending:
+                raise RuntimeError("jobs pending with nothing live or retiring: the budget cannot hold them")
+        self.drain()
         return self.stats()
 
     def stats(self):
@@ -227,6 +298,7 @@ class Server:
     def checkpoint(self):
         """Host copy of every live job (packed lattice and sweep counter) and
         the queue; the device state can then be dropped."""
+        self.drain()
         self.backend.synchronize()
         live = []
         for j in self.live:

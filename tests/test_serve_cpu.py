@@ -46,6 +46,15 @@ class FakeBackend:
     def synchronize(self):
         pass
 
+    def record(self):
+        return self.clock.t
+
+    def wait(self, ev):
+        pass
+
+    def elapsed(self, a, b):
+        return b - a
+
     def finish(self, h, corr):
         return {"t": h["t"]}
 
@@ -125,3 +134,58 @@ def test_checkpoint_restore_gives_the_same_results():
     srv2.run_trace(rest)
     got = {j.job_id: j.digest for j in srv2.finished}
     assert got == ref
+
+
+def test_ticks_in_flight_are_bounded_and_each_waited_once():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    waited = []
+    be.wait = waited.append
+    srv = Server(backend=be, hbm_budget=2**26, tick_seconds=0.001, clock=clock, rate_guess=1e10, depth=2)
+    depths = []
+    tick = srv.tick
+
+    def counting_tick():
+        r = tick()
+        depths.append(len(srv._inflight))
+        return r
+
+    srv.tick = counting_tick
+    st = srv.run_trace(poisson_trace(30, rate_per_s=2000, L_log2=(6, 9), sweeps_log10=(1, 2.5)))
+    assert st["jobs"] == 30 and srv.ticks > 5
+    assert max(depths) <= 2
+    assert len(waited) == srv.ticks                  # one wait per tick, after later ticks were queued
+    assert srv.in_use == 0 and not srv._inflight and not srv._retiring
+
+
+def test_retirement_runs_beside_later_ticks():
+    """The first job's retirement blocks until two more ticks have been
+    queued: with retirement on the main thread this would never happen."""
+    import threading
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    go = threading.Event()
+    calls = []
+    sweep = be.group_sweep
+
+    def group_sweep(handles, n, betas, Ds):
+        sweep(handles, n, betas, Ds)
+        calls.append(len(handles))
+        if len(calls) >= 3:
+            go.set()
+
+    finish = be.finish
+
+    def finish_after_two_more_ticks(h, corr):
+        if h["job"] == 0:
+            assert go.wait(timeout=10), "later ticks were not queued while a job retired"
+        return finish(h, corr)
+
+    be.group_sweep = group_sweep
+    be.finish = finish_after_two_more_ticks
+    srv = Server(backend=be, hbm_budget=2**26, tick_seconds=0.001, clock=clock, rate_guess=1e10, max_chunk=1)
+    jobs = [Job(0, 0, 64, 1, 0.4, 0.0, 1, arrival=0.0), Job(1, 0, 64, 2, 0.4, 0.0, 6, arrival=0.0)]
+    srv.run_trace(jobs)
+    done = {j.job_id: j for j in srv.finished}
+    assert set(done) == {0, 1} and done[0].result["t"] == 1 and done[1].result["t"] == 6
+    assert len(calls) >= 3
