@@ -36,31 +36,108 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(budget_s=12.0):
-    """The oracle on the host cores: Ising at T_c from a random start on an
-    L = 2^13 sample of the workload, whole sweeps until ~budget_s elapse."""
-    import oracle
+def host_cpu():
+    """CPU model (lscpu's "Model name", read from /proc/cpuinfo), nproc and
+    the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
         cores = os.cpu_count() or 1
-    L = 2 ** 13
-    s = oracle.init(oracle.ISING, L, 1002)
-    done, t0 = 0, time.perf_counter()
-    while True:
-        oracle.sweep(s, oracle.ISING, 1002, done, 1, BETA_C, 0.0, nthreads=cores)
-        done += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or done >= 16:
-            break
-    # the same sample on one thread (two more sweeps)
-    t1 = time.perf_counter()
-    oracle.sweep(s, oracle.ISING, 1002, done, 2, BETA_C, 0.0, nthreads=1)
-    el1 = time.perf_counter() - t1
-    return {"value": round(L * L * done / (el * 1e9), 5), "unit": "updates/ns", "cores": cores, "kind": "oracle",
-            "sample": "Ising L=2^13 at T_c from a random start, %d sweeps (%.1f s), rows of one colour split over "
-                      "%d OpenMP threads" % (done, el, cores),
-            "single_thread_value": round(L * L * 2 / (el1 * 1e9), 5)}
+    return {"model": model, "nproc": os.cpu_count(), "cores": cores}
+
+
+def _time_oracle_sweeps(model, L, seed, n, beta, D, threads):
+    """Seconds of n oracle sweeps of a T = infinity start (i.i.d. +-1, or
+    uniform over -1/0/+1 for Blume-Capel), drawn here with numpy: the sweep's
+    cost does not depend on which sample it gets, and the oracle's own
+    initialisation (one Philox block per site, one thread) would take longer
+    than the sweeps."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(seed)
+    vals = np.array([-1, 0, 1] if model == oracle.BC else [-1, 1], dtype=np.int8)
+    s = vals[rng.integers(0, len(vals), size=(L, L))]
+    t0 = time.perf_counter()
+    oracle.sweep(s, model, seed, 0, n, beta, D, nthreads=threads)
+    return time.perf_counter() - t0
+
+
+def _time_oracle_quench(threads):
+    """The parity-size workload in full: Ising L = 256, seed 1001, 0.9 T_c,
+    random start, 1000 sweeps, B/M and full C(r) along both axes at t = 2^k."""
+    import oracle
+    L, seed, beta, total = 256, 1001, BETA_C / 0.9, 1000
+    s = oracle.init(oracle.ISING, L, seed)
+    t0 = time.perf_counter()
+    done = 0
+    for t in oracle.schedule_pow2(total) + [total]:
+        oracle.sweep(s, oracle.ISING, seed, done, t - done, beta, nthreads=threads)
+        done = t
+        if t < total:
+            oracle.measure(s, threads)
+            oracle.corr(s, oracle.CORR_FULL, oracle.rset(oracle.CORR_FULL, L, t), threads)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(full=False):
+    """The oracle timed on the host cores, single-threaded and with the rows
+    of one colour split over every core (same results either way):
+    - the parity-size workload in full (Ising L = 256, 1000 sweeps, full C(r)
+      at t = 2^k), both ways;
+    - Ising at T_c, one sweep: L = 2^15 on all cores (value = this rate, the
+      headline workload's update at a size the oracle sweeps in seconds) and
+      L = 2^14 on one thread;
+    - Blume-Capel at T = 1.4, D = 1, one sweep of L = 2^15 on all cores.
+    With full, the whole timing plan instead: Ising L = 2^15 and 2^17 (one
+    sweep) and Blume-Capel L = 2^16 (two sweeps), each both ways (about ten
+    minutes of single-threaded sweeps)."""
+    import oracle
+    cpu = host_cpu()
+    n_all = cpu["cores"]
+    legs = []
+
+    def leg(name, updates, secs, threads):
+        legs.append({"workload": name, "threads": threads, "seconds": round(secs, 3),
+                     "updates_per_ns": round(updates / (secs * 1e9), 5)})
+        log("  oracle %s, %d thread(s): %.2f s" % (name, threads, secs))
+
+    def ising(L, th):
+        leg("Ising L=2^%d at T_c, 1 sweep" % int(math.log2(L)), float(L) * L,
+            _time_oracle_sweeps(oracle.ISING, L, 1002, 1, BETA_C, 0.0, th), th)
+
+    def bc(L, n, th):
+        leg("Blume-Capel L=2^%d, T=1.4, D=1, %d sweep(s)" % (int(math.log2(L)), n), float(L) * L * n,
+            _time_oracle_sweeps(oracle.BC, L, 1003, n, 1 / 1.4, 1.0, th), th)
+
+    for th in (1, n_all):
+        leg("Ising L=256, 1000 sweeps, full C(r) at t=2^k", 256.0 * 256 * 1000, _time_oracle_quench(th), th)
+    ising(2 ** 15, n_all)
+    head = legs[-1]
+    if full:
+        ising(2 ** 15, 1)
+        for th in (n_all, 1):
+            ising(2 ** 17, th)
+        for th in (n_all, 1):
+            bc(2 ** 16, 2, th)
+    else:
+        ising(2 ** 14, 1)
+        bc(2 ** 15, 1, n_all)
+    single = next(x for x in legs if x["workload"].startswith("Ising L=2^1") and x["threads"] == 1)
+    return {"value": head["updates_per_ns"], "unit": "updates/ns", "cores": n_all, "kind": "oracle",
+            "sample": "%s with the rows of one colour split over %d OpenMP threads; legs lists every timing"
+                      % (head["workload"], n_all),
+            "single_thread_value": single["updates_per_ns"], "single_thread_sample": single["workload"],
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "legs": legs}
 
 
 def kernel_source_sha():
@@ -314,6 +391,22 @@ def run_batched(args):
     mcl.group_sweep(lats, [n] * len(lats), betas, Ds)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
+    # the same call with one persistent launch per colour for every replica
+    # (4 workgroups per CU walking the tile list) replayed from a captured
+    # graph, whatever the tuner chose
+    from paper_2502_18624_amd.autotune import get_tuning, set_tuning, tuning_dict, tuning_from_dict
+    tuned = get_tuning()
+    pg = tuning_from_dict(dict(tuning_dict(tuned), split_models=0, wg_per_cu=4, use_graph=1, graph_sweeps=32))
+    set_tuning(pg)
+    mcl.group_sweep(lats, [1] * len(lats), betas, Ds)           # warm-up
+    mcl.group_sweep(lats, [1] * len(lats), betas, Ds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mcl.group_sweep(lats, [n] * len(lats), betas, Ds)           # a new shape: plain launches, then seen once
+    mcl.group_sweep(lats, [n] * len(lats), betas, Ds)           # seen twice: captured and replayed
+    torch.cuda.synchronize()
+    t_pg = time.perf_counter() - t0
+    set_tuning(tuned)
     t0 = time.perf_counter()
     for k in range(n):
         for lat, b, d in zip(lats, betas, Ds):
@@ -328,6 +421,9 @@ def run_batched(args):
             "batched_updates_per_ns": round(upd / (t_batched * 1e9), 2),
             "plain_updates_per_ns": round(upd / (t_plain * 1e9), 2),
             "batched_over_plain": round(t_plain / t_batched, 3),
+            "persistent_graph_updates_per_ns": round(2 * upd / (t_pg * 1e9), 2),
+            "persistent_graph": "one launch per colour for all replicas, 4 workgroups per CU, 32-sweep graph "
+                                "replays (two calls of %d sweeps; the second replays the captured graph)" % n,
             "tuning": {k: v for k, v in tune.items() if k != "rows_log2L"} | {
                 "rows_by_L": {str(2 ** k): tune["rows_log2L"][k] for k in range(9, 14)}}}
 
@@ -335,24 +431,33 @@ def run_batched(args):
 def run_serving(args):
     """Poisson stream of quench jobs through the continuous-batching server:
     the first `serve_jobs` arrivals at 200 jobs/s (offered load far above one
-    GPU), then a trace at about 70% of the measured batched rate."""
+    GPU), then `serve_sustainable_jobs` arrivals at about 70% of the rate the
+    first trace measured."""
     from paper_2502_18624_amd.serve import Server, poisson_trace
     out = {}
     mean_work = None
-    for name, rate in (("poisson_200_per_s", 200.0), ("sustainable", None)):
+    for name, rate, count in (("poisson_200_per_s", 200.0, args.serve_jobs),
+                              ("sustainable", None, args.serve_sustainable_jobs)):
         if rate is None:
             cap = out["poisson_200_per_s"]["updates_per_ns"] * 1e9
             rate = 0.7 * cap / mean_work
-        jobs = poisson_trace(args.serve_jobs, rate_per_s=rate, seed=4)
-        mean_work = sum(j.updates for j in jobs) / len(jobs)
+        jobs = poisson_trace(count, rate_per_s=rate, seed=4)
+        if mean_work is None:
+            mean_work = sum(j.updates for j in jobs) / len(jobs)
+        log("  serving %s: %d jobs at %.2f jobs/s" % (name, count, rate))
         # no result digests here: they copy each finished lattice to the host (a test aid)
         srv = Server(hbm_budget=250e9, tick_seconds=0.02, keep_digest=False)
         st = srv.run_trace(jobs)
         st["rate_per_s"] = round(rate, 3)
+        st["arrival_window_s"] = round(max(j.arrival for j in jobs), 3)
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        log("  serving %s: p50 %.2f s, p99 %.2f s, %.1f updates/ns" % (
+            name, st["latency_p50_s"], st["latency_p99_s"], st["updates_per_ns"]))
     out["workload"] = ("Poisson quench jobs (Ising/Blume-Capel 50/50), L = 64 round(2^U[10,15]/64), sweeps = "
                        "round(10^U[2,4]), T ~ U[0.5,1.5] T_c, D in {0,0.5,1}, admitted by footprint up to 250 GB; "
-                       "first %d arrivals" % args.serve_jobs)
+                       "first %d arrivals at 200 jobs/s, then %d at 70%% of the measured rate; one event per tick, "
+                       "up to two ticks queued, retirement beside later ticks" % (
+                           args.serve_jobs, args.serve_sustainable_jobs))
     return out
 
 
@@ -469,6 +574,8 @@ def main():
     ap.add_argument("--schedule", choices=("pow2", "paper"), default="pow2",
                     help="measurement times of the headline quench: t = 2^k, or the paper's floor(2^(x/8) + 0.5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle on every workload of the plan (adds minutes of single-threaded sweeps)")
     ap.add_argument("--no-extras", action="store_true", help="only the Ising L=2^17 quench")
     ap.add_argument("--extras", default="bc,lut,batched,serving,scan",
                     help="comma list of the further legs: bc, lut, batched, serving, scan")
@@ -477,7 +584,8 @@ def main():
     ap.add_argument("--lut-sweeps", type=int, default=2000)
     ap.add_argument("--replicas", type=int, default=512)
     ap.add_argument("--batched-sweeps", type=int, default=100)
-    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-jobs", type=int, default=300)
+    ap.add_argument("--serve-sustainable-jobs", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -503,7 +611,7 @@ def main():
         res["scan"] = run_scan(args)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
-        res["cpu_baseline"] = cpu_baseline()
+        res["cpu_baseline"] = cpu_baseline(full=args.cpu_full)
     print(json.dumps(res), flush=True)
 
 
