@@ -25,8 +25,7 @@ struct mcl_lattice {
     int32_t* rdev;       // device: distances, rcap entries
     int64_t* Cx;         // device: rcap entries
     int64_t* Cy;         // device: rcap entries
-    int32_t* res;        // device: 17 offsets + rcap positions, sampled distances grouped by r mod 16
-    int8_t* zs;          // device: (L/16)^2 sampled sources as int8
+    uint32_t* tbits;     // device: T bits of the sampled columns (measure scratch)
     void* lutb;          // device: bucket table of the 1-bit mode (1-bit lattices only)
     uint32_t* tdev;      // device: sweep index at the start of a replayed graph
     int64_t rcap;
@@ -70,7 +69,7 @@ int cell_bits(int model) { return model == MCL_ISING_LUT ? 1 : 4; }
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-    int64_t planes, acc, rlist, cx, cy, res, zs, ctl, lutb, total, rcap;
+    int64_t planes, acc, rlist, cx, cy, tbits, ctl, lutb, total, rcap;
 };
 
 Layout layout_of(int model, int64_t L)
@@ -88,10 +87,8 @@ Layout layout_of(int model, int64_t L)
     off += align256(lay.rcap * 8);
     lay.cy = off;
     off += align256(lay.rcap * 8);
-    lay.res = off;
-    off += align256((lay.rcap + 17) * 4);
-    lay.zs = off;
-    off += align256((L / 16) * (L / 16));
+    lay.tbits = off;
+    off += align256(mcl::tbits_bytes(model, L));
     lay.ctl = off;
     off += 256;
     lay.lutb = off;
@@ -963,8 +960,7 @@ int lattice_init(mcl_lattice** out, int model, int64_t L, uint64_t seed, int ini
     h->rdev = (int32_t*)(base + lay.rlist);
     h->Cx = (int64_t*)(base + lay.cx);
     h->Cy = (int64_t*)(base + lay.cy);
-    h->res = (int32_t*)(base + lay.res);
-    h->zs = (int8_t*)(base + lay.zs);
+    h->tbits = (uint32_t*)(base + lay.tbits);
     h->lutb = model == MCL_ISING_LUT ? (void*)(base + lay.lutb) : nullptr;
     h->tdev = (uint32_t*)(base + lay.ctl);
     h->rcap = lay.rcap;
@@ -1039,44 +1035,22 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         MCL_HIP(mcl::launch_zero(h->Cx, nr, h->stream));
         MCL_HIP(mcl::launch_zero(h->Cy, nr, h->stream));
     }
-    MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, h->stream));
-    // The host buffer of residue lists must outlive the asynchronous copy:
-    // it lives until the synchronisation below.
-    std::vector<int32_t> res;
+    const int ns = nr - n_all;                          // sampled distances
+    MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, ns > 0 ? h->tbits : nullptr, h->stream));
     if (nr > 0) {
         // every-source distances are r = 0 .. n_all - 1 (position j holds r = j)
         const int rshort = std::min(n_all - 1, 32);
         MCL_HIP(mcl::launch_corr_short(h->g, h->model, rshort, h->Cx, h->Cy, h->stream));
         if (n_all - 1 > 32)
             MCL_HIP(mcl::launch_corr_all(h->g, h->rdev + 33, n_all - 33, h->Cx + 33, h->Cy + 33, h->stream));
-        const int ns = nr - n_all;
         if (ns > 0) {
-            // group the sampled distances by r mod 16 (positions within the sampled sub-list)
-            res.assign(17 + ns, 0);
-            int maxc = 0;
-            for (int rho = 0, pos = 17; rho < 16; ++rho) {
-                res[rho] = pos - 17;
-                int cnt = 0;
-                for (int j = 0; j < ns; ++j)
-                    if ((r[n_all + j] & 15) == rho) {
-                        res[pos++] = j;
-                        ++cnt;
-                    }
-                maxc = std::max(maxc, cnt);
-            }
-            res[16] = ns;
-            MCL_HIP(hipMemcpyAsync(h->res, res.data(), res.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                   h->stream));
             mcl::SampledArgs sa;
             sa.r = h->rdev + n_all;
             sa.nr = ns;
             sa.Cx = h->Cx + n_all;
             sa.Cy = h->Cy + n_all;
-            sa.zs = h->zs;
-            sa.res_off = h->res;
-            sa.res_idx = h->res + 17;
-            sa.max_per_residue = maxc;
-            MCL_HIP(mcl::launch_corr_sampled(h->g, sa, h->stream));
+            sa.tbits = h->tbits;
+            MCL_HIP(mcl::launch_corr_sampled(h->g, h->model, sa, h->stream));
         }
     }
     int64_t acc[mcl::kAccSlots];

@@ -51,25 +51,31 @@ hipError_t launch_set_word(uint32_t* p, uint32_t v, bool add, hipStream_t s);
 // (corrupted) are L^2 minus the three counts.
 constexpr int kAccSlots = 16;
 hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s);
-hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s);
+// T bits of the sampled columns x = 0 mod 16: for every row y, bit j of
+// word k is [s(16 (32 k + j), y) = +1] (and, Blume-Capel only, a second
+// plane of [s != 0] after L rows); tbits_words(L) words per row, the L / 16
+// bits of a row repeated to fill one word below L = 512 (L is a power of
+// two wherever they are used; other L get room for ceil(L / 512) words).
+inline int64_t tbits_words(int64_t L) { return L >= 512 ? (L + 511) / 512 : 1; }
+inline int64_t tbits_bytes(int model, int64_t L) { return (model == 1 ? 2 : 1) * L * tbits_words(L) * 4; }
+// B, M, Q, counts and the sigma-h histogram into acc; with tbits set, also
+// the T bits of every row (written by the same pass from L = 512 on).
+hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s);
 // Correlations from every source at r = 0..R (R <= 32), LDS-tiled.
 hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s);
 // Correlations from every source at distances r[0..nr) (any r <= L/2).
 hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
                            hipStream_t s);
-// Correlations from the sampled sources x = y = 0 (mod 16) at r[0..nr).
-// res_off[17] / res_idx group the positions j of the distances by r_j mod 16.
+// Correlations from the sampled sources x = y = 0 (mod 16) at r[0..nr), from
+// the lattice (x) and the T bits of the B/M/Q pass (y).
 struct SampledArgs {
     const int32_t* r;
     int nr;
     int64_t* Cx;
     int64_t* Cy;
-    int8_t* zs;              // (L/16)^2 bytes of scratch
-    const int32_t* res_off;
-    const int32_t* res_idx;
-    int max_per_residue;
+    const uint32_t* tbits;
 };
-hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s);
+hipError_t launch_corr_sampled(const Geom& g, int model, const SampledArgs& a, hipStream_t s);
 
 // Batched half-sweep.  One descriptor per replica (64 bytes).  The work of
 // a launch is a list of tiles of 256 threads; replica i owns the tiles

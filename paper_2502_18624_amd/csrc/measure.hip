@@ -215,14 +215,61 @@ __device__ __forceinline__ uint32_t sd_add_ising4(uint32_t o, uint32_t a, uint32
     return popc(p0) + 2u * popc(p1) + 4u * popc(p2);
 }
 
+// T bits (the sampled columns, see below) of row y from the thread's
+// vector v of the row's colour-(y & 1) plane: 4-bit cells, vector q holds
+// the cells 8 a for a = 4 q .. 4 q + 3 at nibble 0 of its words, and 8 lanes
+// make one word; 1-bit cells, vector q holds a = 16 q .. 16 q + 15 at bits
+// 0, 8, 16, 24 of its words, and 2 lanes make one word.  The lanes of a
+// word share the row (Q is a multiple of 8, resp. 2, from L = 512 on).
+template <int MODEL>
+__device__ __forceinline__ void emit_tbits(const uint4& v, uint32_t q, uint32_t y, uint32_t L,
+                                           uint32_t* __restrict__ tb)
+{
+    const uint32_t NSW = L >> 9;
+    if (MODEL == 2) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t x = pick(v, d) & 0x01010101u;
+            bits |= ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu) << (4 * d);
+        }
+        uint32_t w = bits << (16u * (q & 1u));
+        w |= __shfl_xor(w, 1);
+        if ((q & 1u) == 0) tb[(size_t)y * NSW + (q >> 1)] = w;
+        return;
+    }
+    uint32_t sb = 0, zb = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        sb |= ((pick(v, d) >> 1) & 1u) << d;       // n = 2: s = +1
+        zb |= ((~pick(v, d)) & 1u) << d;           // n != 1: s != 0
+    }
+    const uint32_t sh = 4u * (q & 7u);
+    uint32_t ws = sb << sh, wz = zb << sh;
+    ws |= __shfl_xor(ws, 1);
+    ws |= __shfl_xor(ws, 2);
+    ws |= __shfl_xor(ws, 4);
+    if (MODEL == 1) {
+        wz |= __shfl_xor(wz, 1);
+        wz |= __shfl_xor(wz, 2);
+        wz |= __shfl_xor(wz, 4);
+    }
+    if ((q & 7u) == 0) {
+        tb[(size_t)y * NSW + (q >> 3)] = ws;
+        if (MODEL == 1) tb[(size_t)(L + y) * NSW + (q >> 3)] = wz;
+    }
+}
+
 // One pass over both planes: B and M, Q and the value counts, and the
-// Schwinger-Dyson histogram (section 4) of sigma h over every site.  A task
-// is a column vector q of a band of rows; the thread keeps rows y - 1, y,
-// y + 1 of both planes.  Colour-0 sites carry the bonds (each bond has one
-// colour-0 end); both colours add to the counts and the histogram.
+// Schwinger-Dyson histogram (section 4) of sigma h over every site; with tb
+// set (L >= 512), also the T bits of every row.  A task is a column vector
+// q of a band of rows; the thread keeps rows y - 1, y, y + 1 of both
+// planes.  Colour-0 sites carry the bonds (each bond has one colour-0
+// end); both colours add to the counts and the histogram.
 template <int MODEL>
 __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
-                                                  uint32_t L, uint32_t rows, int64_t* __restrict__ acc)
+                                                  uint32_t L, uint32_t rows, int64_t* __restrict__ acc,
+                                                  uint32_t* __restrict__ tb)
 {
     constexpr int CB = MODEL == 2 ? 1 : 4;
     using C = Cell<CB>;
@@ -248,6 +295,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
             const size_t yd = (y + 1 == L) ? 0 : y + 1;
             const uint4 adn = a4[yd * Q], bdn = b4[yd * Q];
             const bool odd = (y & 1u) != 0;      // colour-0 sites of row y have x = 2 i + (y & 1)
+            if (tb) emit_tbits<MODEL>(odd ? bmid : amid, q, y, L, tb);
             // colour 0 looks right (i + 1) on odd rows, colour 1 on even rows
             const uint32_t bhalo = p1[(size_t)y * W + (odd ? hwr : hwl)];
             const uint32_t ahalo = p0[(size_t)y * W + (odd ? hwl : hwr)];
@@ -556,106 +604,194 @@ __global__ __launch_bounds__(256) void corr_all_kernel(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Correlations, sampled sources.  Zs[b * (L / 16) + a] = s(16 a, 16 b) as int8.
+// Correlations, sampled sources (x = y = 0 mod 16), as bits.
+//
+// T bits: for every row y, bit j of word k of row y (plane 0) is
+// [s(16 a, y) = +1] with a = 32 k + j, and for Blume-Capel plane 1 holds
+// [s(16 a, y) != 0]; a row has tbits_words(L) = max(1, L / 512) words, and
+// below L = 512 the NS = L / 16 bits of a row repeat to fill the word (NS
+// divides 32), so a rotation by m of the word is a shift by m mod NS.  The
+// site (16 a, y) has colour y & 1 and in-plane index 8 a.
+//
+// A sum of s s' over the pairs of two such words is, with the mask z of the
+// pairs that count (both nonzero, and inside the row), popc(z) - 2
+// popc(z & (a ^ b)): a product is +1 for equal signs and -1 otherwise.
 // ---------------------------------------------------------------------------
-// The source (16 a, 16 b) is in-plane cell 8 a of row 16 b of plane 0.
-template <int CB>
-__global__ __launch_bounds__(256) void zs_build_kernel(const uint32_t* __restrict__ plane0, uint32_t L,
-                                                       int8_t* __restrict__ zs)
+template <int MODEL>
+__device__ __forceinline__ int sampled_pairs(uint32_t s, uint32_t sz, uint32_t p, uint32_t pz, uint32_t valid,
+                                             bool full)
 {
-    const uint32_t W = L >> Cell<CB>::kWordShift;
-    const uint64_t ns = L >> 4;                  // sources per row and source rows
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ns * ns;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = g / ns, a = g - b * ns;
-        zs[g] = (int8_t)Cell<CB>::spin(plane0 + (size_t)16 * b * W, (uint32_t)(8 * a));
+    if (MODEL == 1) {
+        const uint32_t z = sz & pz & valid;
+        return (int)popc(z) - 2 * (int)popc(z & (s ^ p));
+    }
+    if (full) return 32 - 2 * (int)popc(s ^ p);
+    return (int)popc(valid) - 2 * (int)popc(valid & (s ^ p));
+}
+
+// T bits of one row, any L: thread per output word (the bits of 32
+// sources, or of NS repeated).  Used below L = 512, where the B/M/Q pass
+// does not write them.
+template <int MODEL>
+__global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                    uint32_t* __restrict__ tb)
+{
+    using C = Cell<MODEL == 2 ? 1 : 4>;
+    const uint32_t W = L >> C::kWordShift, NS = L >> 4;
+    const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
+    const size_t plane_words = (size_t)L * W;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < L * NSW; g += gridDim.x * blockDim.x) {
+        const uint32_t y = g / NSW, k = g - y * NSW;
+        const uint32_t* row = planes + (y & 1u) * plane_words + (size_t)y * W;
+        uint32_t sb = 0, zb = 0;
+        for (uint32_t j = 0; j < 32; ++j) {
+            const int s = C::spin(row, 8u * ((32u * k + j) % NS));
+            sb |= (s > 0 ? 1u : 0u) << j;
+            zb |= (s != 0 ? 1u : 0u) << j;
+        }
+        tb[g] = sb;
+        if (MODEL == 1) tb[(size_t)L * NSW + g] = zb;
     }
 }
 
-// Along x, one source row y = 16 b at a time (persistent over rows).  The
-// row is unpacked into LDS residue by residue, R_rho[a] = s(16 a + rho, y)
-// (P = L / 16 bytes each, L a power of two), so the partners of the sources
-// 16 a, a = 4 q .. 4 q + 3, at distance r are the bytes R_{r mod 16}[4 q +
-// (r >> 4) ...]: one v_alignbyte_b32 of two LDS words, and the four
-// products are one v_dot4.  LDS holds R_0 (the sources) and the residues
-// rho0 .. rho0 + G - 1; a launch handles the distances of those residues
-// (the host runs 16 / G passes when the whole row does not fit).  Wave w
-// owns the distances k = w, w + 16, ... and sweeps all sources of the row
-// for each, so it reduces once per distance and row.
-template <int CB>
-__global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restrict__ planes, uint32_t L,
-                                                      const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
-                                                      uint32_t G, int64_t* __restrict__ Cx)
+// Along x, one sampled row y = 16 b at a time (persistent over rows).  The
+// row's cells go into LDS as residue rows of bits: R_rho bit a is the cell
+// (16 a + rho, y).  R_0 holds the sources, and the partners of distance
+// r = 16 m + rho are R_rho shifted by m: per word of 32 sources one funnel
+// shift, one xor and the bit counts.  LDS holds R_0 and the residues rho0 ..
+// rho0 + G - 1 (the host runs 16 / G passes when a row of all 16 residues
+// does not fit).  Wave w owns the distances k = w, w + 16, ... and sums
+// them over all words of the row.
+//
+// Building the residue rows (L >= 512): a 4-bit word w of plane c holds the
+// cells x = 16 w + 2 j + c, j = 0 .. 7, i.e. bit w of residues 2 j + c, so a
+// wave's 64 words give 64 bits of each of its residues by one ballot per j.
+// A 1-bit word w of plane c holds x = 64 w + 2 k + c: bit k belongs to
+// residue 2 (k & 7) + c at position 4 w + (k >> 3), four bits per residue,
+// gathered per lane and merged over 8 lanes.
+__device__ __forceinline__ int sx_row(uint32_t rho, uint32_t rho0, uint32_t G)
 {
-    // LDS: nr int32 sums, the nr distances, R_0, then R_rho0 .. R_{rho0+G-1}
-    extern __shared__ int sx_lds[];
-    int* sums = sx_lds;
-    int* rl = sx_lds + nr;
-    const uint32_t W = L >> Cell<CB>::kWordShift;
-    const uint32_t P = L >> 4;                      // bytes per residue class
-    const uint32_t PQ = P >> 2;                     // words per residue class (a power of two)
-    int8_t* zrow = reinterpret_cast<int8_t*>(sx_lds + 2 * nr);
-    int8_t* grow = zrow + P;
-    const uint32_t* zrow_w = reinterpret_cast<const uint32_t*>(zrow);
-    const uint32_t* grow_w = reinterpret_cast<const uint32_t*>(grow);
-    const size_t plane_vecs = (size_t)L * (W >> 2);
-    const uint4* P4 = reinterpret_cast<const uint4*>(planes);
+    return rho - rho0 < G ? (int)(1 + rho - rho0) : -1;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+                                                       const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
+                                                       uint32_t G, int64_t* __restrict__ Cx)
+{
+    constexpr int NB = MODEL == 1 ? 2 : 1;
+    using C = Cell<MODEL == 2 ? 1 : 4>;
+    extern __shared__ int sxb_lds[];
+    int* sums = sxb_lds;
+    int* rl = sxb_lds + nr;
+    uint32_t* R = reinterpret_cast<uint32_t*>(sxb_lds + 2 * nr);    // [(1 + G) rows][NB][NSW]
+    const uint32_t W = L >> C::kWordShift, NS = L >> 4;
+    const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
+    const uint32_t rowstride = NB * NSW;
+    const bool full = L >= 512;
+    const uint32_t valid = full ? 0xFFFFFFFFu : (NS >= 32 ? 0xFFFFFFFFu : ((1u << NS) - 1u));
+    const size_t plane_words = (size_t)L * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
     for (int k = threadIdx.x; k < nr; k += blockDim.x) {
         sums[k] = 0;
         rl[k] = rlist[k];
     }
-    for (uint32_t b = blockIdx.x; b < (L >> 4); b += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < NS; b += gridDim.x) {
         const uint32_t y = 16 * b;
         __syncthreads();
-        // 16-byte vectors of both plane rows (W is a multiple of 4)
-        for (uint32_t idx = threadIdx.x; idx < (W >> 1); idx += blockDim.x) {
-            const uint32_t c = idx >= (W >> 2) ? 1u : 0u;
-            const uint32_t v4 = idx - c * (W >> 2);
-            const uint4 v = P4[c * plane_vecs + (size_t)y * (W >> 2) + v4];
-            const uint32_t par = (y + c) & 1u;              // x = 2 i + par
+        if (L < 512) {
+            // one word per residue row, its NS bits repeated
+            for (uint32_t t = threadIdx.x; t < (1 + G) * NB; t += blockDim.x) {
+                const uint32_t rr = t / NB, plane = t - rr * NB;
+                const uint32_t rho = rr == 0 ? 0u : rho0 + rr - 1;
+                const uint32_t c = rho & 1u;                     // (x + y) & 1 with y even
+                const uint32_t* row = planes + c * plane_words + (size_t)y * W;
+                uint32_t v = 0;
+                for (uint32_t j = 0; j < 32; ++j) {
+                    const int s = C::spin(row, (16u * (j % NS) + rho) >> 1);
+                    v |= ((plane == 0 ? s > 0 : s != 0) ? 1u : 0u) << j;
+                }
+                R[rr * rowstride + plane * NSW] = v;
+            }
+        } else if (C::kPerWord == 8) {
+            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+                const uint32_t c = idx >= W ? 1u : 0u;
+                const uint32_t w = idx - c * W;
+                const uint32_t word = planes[c * plane_words + (size_t)y * W + w];
+                // lanes 0..31 and 32..63 cover 32 words each, of one plane each
+                const uint32_t idx0 = idx - (uint32_t)lane;
+                const uint32_t c_lo = idx0 >= W ? 1u : 0u, c_hi = idx0 + 32 >= W ? 1u : 0u;
+                const uint32_t k_lo = (idx0 - c_lo * W) >> 5, k_hi = (idx0 + 32 - c_hi * W) >> 5;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const uint32_t word = pick(v, d);
-                const uint32_t wd = 4 * v4 + d;
+                for (int j = 0; j < 8; ++j) {
+                    const uint64_t ms = __ballot((word >> (4 * j + 1)) & 1u);
+                    uint64_t mz = 0;
+                    if (NB == 2) mz = __ballot(((~word) >> (4 * j)) & 1u);
+                    if (lane == 0) {
+                        const uint32_t rl_lo = 2 * j + c_lo, rl_hi = 2 * j + c_hi;
+                        const int r_lo = sx_row(rl_lo, rho0, G), r_hi = sx_row(rl_hi, rho0, G);
+                        if (r_lo >= 0) {
+                            R[r_lo * rowstride + k_lo] = (uint32_t)ms;
+                            if (NB == 2) R[r_lo * rowstride + NSW + k_lo] = (uint32_t)mz;
+                        }
+                        if (r_hi >= 0) {
+                            R[r_hi * rowstride + k_hi] = (uint32_t)(ms >> 32);
+                            if (NB == 2) R[r_hi * rowstride + NSW + k_hi] = (uint32_t)(mz >> 32);
+                        }
+                        if (rl_lo == 0) {                            // the sources
+                            R[k_lo] = (uint32_t)ms;
+                            if (NB == 2) R[NSW + k_lo] = (uint32_t)mz;
+                        }
+                        if (rl_hi == 0) {
+                            R[k_hi] = (uint32_t)(ms >> 32);
+                            if (NB == 2) R[NSW + k_hi] = (uint32_t)(mz >> 32);
+                        }
+                    }
+                }
+            }
+        } else {
+            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+                const uint32_t c = idx >= W ? 1u : 0u;
+                const uint32_t w = idx - c * W;
+                const uint32_t word = planes[c * plane_words + (size_t)y * W + w];
 #pragma unroll
-                for (int k = 0; k < Cell<CB>::kPerWord; ++k) {
-                    const uint32_t x = 2 * (Cell<CB>::kPerWord * wd + k) + par;
-                    const int8_t sv = (int8_t)(CB == 4 ? (int)((word >> (4 * k)) & 0xFu) - 1
-                                                       : (((word >> k) & 1u) ? 1 : -1));
-                    const uint32_t rho = x & 15u, a = x >> 4;
-                    if (rho == 0) zrow[a] = sv;
-                    if (rho - rho0 < G) grow[(rho - rho0) * P + a] = sv;
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t x = (word >> j) & 0x01010101u;     // bits j, j + 8, j + 16, j + 24
+                    const uint32_t nib = (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu;
+                    uint32_t v = nib << (4u * (w & 7u));
+                    v |= __shfl_xor(v, 1);
+                    v |= __shfl_xor(v, 2);
+                    v |= __shfl_xor(v, 4);
+                    if ((w & 7u) == 0) {
+                        const uint32_t rho = 2 * j + c;
+                        const int rr = sx_row(rho, rho0, G);
+                        if (rr >= 0) R[rr * rowstride + (w >> 3)] = v;
+                        if (rho == 0) R[w >> 3] = v;
+                    }
                 }
             }
         }
         __syncthreads();
         for (int k = wave; k < nr; k += nwaves) {
             const uint32_t r = (uint32_t)rl[k];
-            if ((r & 15u) - rho0 >= G) continue;            // another pass's residue
-            const uint32_t base = ((r & 15u) - rho0) * PQ;
-            const uint32_t sh = r >> 4;                     // whole sources of offset
-            const uint32_t qs = sh >> 2, bs = sh & 3u;
-            // quads q < PQ - 1 - qs read words q + qs and q + qs + 1 without wrapping:
-            // plain offsets, two quads (q, q + 64) per step; the rest wraps mod PQ
-            const uint32_t qlim = PQ - 1 - qs;
-            const uint32_t* gb = grow_w + base + qs;
-            int acc0 = 0, acc1 = 0;
-            uint32_t q = lane;
-            for (; q + 64 < qlim; q += 128) {
-                acc0 = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)__builtin_amdgcn_alignbyte(gb[q + 1], gb[q], bs),
-                                              acc0, false);
-                acc1 = __builtin_amdgcn_sdot4((int)zrow_w[q + 64],
-                                              (int)__builtin_amdgcn_alignbyte(gb[q + 65], gb[q + 64], bs), acc1, false);
+            const int rr = sx_row(r & 15u, rho0, G);
+            if (rr < 0) continue;                                 // another pass's residue
+            const uint32_t m = r >> 4;
+            const uint32_t ws = m >> 5, sh = m & 31u;
+            const uint32_t* P = R + rr * rowstride;
+            int acc = 0;
+            for (uint32_t w = lane; w < NSW; w += 64) {
+                const uint32_t w0 = (w + ws) & (NSW - 1), w1 = (w0 + 1) & (NSW - 1);
+                const uint32_t p = funnel(P[w1], P[w0], sh);
+                uint32_t sz = 0, pz = 0;
+                if (NB == 2) {
+                    sz = R[NSW + w];
+                    pz = funnel(P[NSW + w1], P[NSW + w0], sh);
+                }
+                acc += sampled_pairs<MODEL>(R[w], sz, p, pz, valid, full);
             }
-            for (; q < PQ; q += 64) {
-                const uint32_t wi = (q + qs) & (PQ - 1);
-                const uint32_t part = __builtin_amdgcn_alignbyte(grow_w[base + ((wi + 1) & (PQ - 1))],
-                                                                 grow_w[base + wi], bs);
-                acc0 = __builtin_amdgcn_sdot4((int)zrow_w[q], (int)part, acc0, false);
-            }
-            const int s2 = wave_sum_i32(acc0 + acc1);
+            const int s2 = wave_sum_i32(acc);
             if (lane == 0) sums[k] += s2;
         }
     }
@@ -664,83 +800,48 @@ __global__ __launch_bounds__(1024) void corr_sx_kernel(const uint32_t* __restric
         if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
 }
 
-// Along y, target-row order: block (residue rho, list chunk, band of rows,
-// source chunk of acw columns).  Target row y' = rho + 16 k pairs with source row
-// b = (y' - r) / 16 for every sampled r = rho (mod 16); the positions of
-// those r in the distance list are res_idx[res_off[rho] ..].  Thread t holds
-// the 4 targets (16 a, y') for a = a0 + 4 t .. + 3 as packed int8.
+// Along y: S_y(r) = sum over the sampled rows b and words k of the pairs of
+// T row 16 b and T row 16 b + r (mod L).  Thread per (source row, word),
+// grid row per chunk of 32 distances; a thread keeps the source word and
+// the 32 distance sums in registers, the target words come from L2.
 constexpr int kYChunk = 32;
-constexpr int kYRows = 128;
 
-template <int CB>
-__global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict__ planes, uint32_t L,
-                                                      const int8_t* __restrict__ zs,
-                                                      const int32_t* __restrict__ rlist,
-                                                      const int32_t* __restrict__ res_off,
-                                                      const int32_t* __restrict__ res_idx, uint32_t nchunk,
-                                                      uint32_t nband, uint32_t nachunk, uint32_t acw,
-                                                      int64_t* __restrict__ Cy)
+template <int MODEL>
+__global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restrict__ tb, uint32_t L,
+                                                       const int32_t* __restrict__ rlist, int nr,
+                                                       int64_t* __restrict__ Cy)
 {
-    const uint32_t W = L >> Cell<CB>::kWordShift;
-    const uint32_t NS = L >> 4;                             // sources per row
-    // Workgroups go round-robin to the 8 XCDs.  The 16 residues of one
-    // (chunk, band, source chunk) read the same source rows for the dense
-    // distances, so they get ids 8 apart: consecutive on one XCD's L2.  The
-    // grid has 128 * ceil(N / 8) workgroups, N = nchunk * nband * nachunk.
-    const uint32_t jdx = blockIdx.x >> 3;
-    const uint32_t rho = jdx & 15u;
-    uint32_t id = ((jdx >> 4) << 3) | (blockIdx.x & 7u);
-    if (id >= nchunk * nband * nachunk) return;
-    const uint32_t ac = id % nachunk;
-    id /= nachunk;
-    const uint32_t band = id % nband;
-    const uint32_t chunk = id / nband;
-    const int p0 = res_off[rho] + (int)(chunk * kYChunk);
-    const int p1 = res_off[rho + 1];
-    if (p0 >= p1) return;
-    // a chunk holds acw source columns (a multiple of 4, at most 4 per thread)
-    const uint32_t a0 = ac * acw + 4u * threadIdx.x;        // first of this thread's 4 columns
-    const bool live = 4u * threadIdx.x < acw && a0 < NS;    // NS is a multiple of 4
-    const size_t plane_words = (size_t)L * W;
+    constexpr int NB = MODEL == 1 ? 2 : 1;
+    const uint32_t NS = L >> 4;
+    const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
+    const uint32_t nsw_log = 31 - __builtin_clz(NSW);
+    const bool full = L >= 512;
+    const uint32_t valid = full ? 0xFFFFFFFFu : (NS >= 32 ? 0xFFFFFFFFu : ((1u << NS) - 1u));
+    const size_t zoff = (size_t)L * NSW;                  // plane 1 (Blume-Capel nonzero bits)
+    const int k0 = blockIdx.y * kYChunk;
+    const int kn = min(kYChunk, nr - k0);
+    uint32_t rr[kYChunk];
     int acc[kYChunk];
-    // r = rho + 16 m for every distance of this residue: the source row of
-    // target row rho + 16 k is k - m (mod L / 16, a power of two).  The shifts
-    // m live in registers, so the 32 source loads of a target row are
-    // independent; slots past the list use m = 0 and are discarded.
-    uint32_t msh[kYChunk];
 #pragma unroll
     for (int k = 0; k < kYChunk; ++k) {
+        rr[k] = k < kn ? (uint32_t)rlist[k0 + k] : 0u;
         acc[k] = 0;
-        const int p = p0 + k;
-        msh[k] = p < p1 ? ((uint32_t)rlist[res_idx[p]] - rho) >> 4 : 0u;
     }
-    const uint32_t nrows = L >> 4;                          // target rows per residue, and source rows
-    const int8_t* zcol = zs + a0;
-    for (uint32_t kk = 0; kk < kYRows; ++kk) {
-        const uint32_t krow = band * kYRows + kk;
-        if (krow >= nrows || !live) break;
-        const uint32_t yt = rho + 16 * krow;
-        // targets (16 a, yt), a = a0 .. a0 + 3: in-plane cells 8 a of row yt in
-        // plane yt & 1, packed as int8 spins
-        const uint32_t* trow = planes + (yt & 1u) * plane_words + (size_t)yt * W;
-        int tp;
-        if (CB == 4) {
-            const uint4 tw = *reinterpret_cast<const uint4*>(trow + a0);
-            const uint32_t t0 = ((tw.x & 0xFu) - 1u) & 0xFFu, t1 = ((tw.y & 0xFu) - 1u) & 0xFFu;
-            const uint32_t t2 = ((tw.z & 0xFu) - 1u) & 0xFFu, t3 = ((tw.w & 0xFu) - 1u) & 0xFFu;
-            tp = (int)(t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
-        } else {
-            // cells 8 a0 .. 8 a0 + 24 are bits 0, 8, 16, 24 of word a0 / 4;
-            // byte = bit ? 0x01 : 0xFF (no carries between bytes)
-            const uint32_t tw = trow[a0 >> 2] & 0x01010101u, nw = tw ^ 0x01010101u;
-            tp = (int)(tw | (shl_opaque<8>(nw) - nw));
+    const uint32_t pairs = NS * NSW;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += gridDim.x * blockDim.x) {
+        const uint32_t b = p >> nsw_log, w = p & (NSW - 1);
+        const uint32_t y = 16 * b;
+        const uint32_t s = tb[(size_t)y * NSW + w];
+        const uint32_t sz = NB == 2 ? tb[zoff + (size_t)y * NSW + w] : 0u;
+#pragma unroll
+        for (int k = 0; k < kYChunk; ++k) {
+            if (k < kn) {
+                const uint32_t yp = (y + rr[k]) & (L - 1);
+                const uint32_t t = tb[(size_t)yp * NSW + w];
+                const uint32_t tz = NB == 2 ? tb[zoff + (size_t)yp * NSW + w] : 0u;
+                acc[k] += sampled_pairs<MODEL>(s, sz, t, tz, valid, full);
+            }
         }
-        int sp[kYChunk];
-#pragma unroll
-        for (int k = 0; k < kYChunk; ++k)
-            sp[k] = *reinterpret_cast<const int*>(zcol + (size_t)((krow - msh[k]) & (nrows - 1)) * NS);
-#pragma unroll
-        for (int k = 0; k < kYChunk; ++k) acc[k] = __builtin_amdgcn_sdot4(sp[k], tp, acc[k], false);
     }
     __shared__ int red[4][kYChunk];
     const int wave = threadIdx.x >> 6;
@@ -750,10 +851,10 @@ __global__ __launch_bounds__(256) void corr_sy_kernel(const uint32_t* __restrict
         if ((threadIdx.x & 63) == 0) red[wave][k] = s2;
     }
     __syncthreads();
-    if (threadIdx.x < kYChunk && p0 + (int)threadIdx.x < p1) {
+    if ((int)threadIdx.x < kn) {
         const int k = threadIdx.x;
         const int64_t tot = (int64_t)red[0][k] + red[1][k] + red[2][k] + red[3][k];
-        if (tot != 0) atomicAdd((unsigned long long*)&Cy[res_idx[p0 + k]], (unsigned long long)tot);
+        if (tot != 0) atomicAdd((unsigned long long*)&Cy[k0 + k], (unsigned long long)tot);
     }
 }
 
@@ -790,19 +891,7 @@ uint32_t grid_cap(uint32_t want)
     return want;
 }
 
-// Source columns per y-correlation workgroup: 1024 (4 per thread), or the
-// multiple of 4 in MCL_SY_CHUNK (read at every launch) when smaller.
-uint32_t sy_chunk()
-{
-    uint32_t w = 1024;
-    if (const char* e = std::getenv("MCL_SY_CHUNK")) {
-        const long long v = std::atoll(e);
-        if (v >= 4 && v < 1024 && (v % 4) == 0) w = (uint32_t)v;
-    }
-    return w;
-}
-
-hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s)
+hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s)
 {
     // bands of 16 to 64 rows: as tall as leaves a full persistent grid
     // (kMaxGrid workgroups of 256 threads) with one task per thread or more;
@@ -813,12 +902,24 @@ hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, hipStream_t s)
     const int64_t threads = g.Q * (g.L / rows);
     const uint32_t grid = grid_cap((uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid));
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
+    // the pass writes the T bits from L = 512 on; below, a kernel of its own
+    uint32_t* tb = g.L >= 512 ? tbits : nullptr;
     if (model == 2)
-        hipLaunchKernelGGL(bmq_kernel<2>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
+        hipLaunchKernelGGL(bmq_kernel<2>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
     else if (model == 1)
-        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
+        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
     else
-        hipLaunchKernelGGL(bmq_kernel<0>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc);
+        hipLaunchKernelGGL(bmq_kernel<0>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !tbits || tb) return e;
+    const uint32_t nw = (uint32_t)(g.L * tbits_words(g.L));
+    const dim3 tg((nw + 255) / 256);
+    if (model == 2)
+        hipLaunchKernelGGL(tbits_kernel<2>, tg, dim3(256), 0, s, g.plane0, L, tbits);
+    else if (model == 1)
+        hipLaunchKernelGGL(tbits_kernel<1>, tg, dim3(256), 0, s, g.plane0, L, tbits);
+    else
+        hipLaunchKernelGGL(tbits_kernel<0>, tg, dim3(256), 0, s, g.plane0, L, tbits);
     return hipGetLastError();
 }
 
@@ -870,59 +971,51 @@ size_t sx_lds_budget()
     return budget;
 }
 
-template <int CB>
+template <int MODEL>
 hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
-    const uint32_t L = (uint32_t)g.L, nb = L / 16;
+    const uint32_t L = (uint32_t)g.L, NS = L / 16;
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
-    const uint64_t nsrc = (uint64_t)nb * nb;
-    // a grid of at most 2^20 workgroups strides over the (L / 16)^2 sources
-    hipLaunchKernelGGL(zs_build_kernel<CB>, dim3((uint32_t)std::min<uint64_t>((nsrc + 255) / 256, 1u << 20)),
-                       dim3(256), 0, s, g.plane0, L, a.zs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // along x: LDS holds the distance sums of a launch, the source residue
-    // and a group of G residue rows (P = L / 16 bytes each)
-    const size_t P = nb, budget = sx_lds_budget();
-    const uint32_t gx = grid_cap(std::min<uint32_t>(nb, 512));
-    // 8 bytes per distance (its sum and its value)
+    constexpr int NB = MODEL == 1 ? 2 : 1;
+    // along x: LDS holds the distance sums of a launch (8 bytes each: the sum
+    // and the distance), the source row and G residue rows of bits
+    const size_t rowb = (size_t)NB * tbits_words(L) * 4, budget = sx_lds_budget();
+    const uint32_t gx = grid_cap(std::min<uint32_t>(NS, 512));
     uint32_t G = 16;
-    while (G > 1 && 8u * 64u + P * (1 + G) > budget) G >>= 1;
-    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(P * (1 + G))) / 8));
-    if (P * (1 + G) + 8 > budget) return hipErrorInvalidValue;
+    while (G > 1 && 8u * 64u + rowb * (1 + G) > budget) G >>= 1;
+    if (rowb * (1 + G) + 8 > budget) return hipErrorInvalidValue;
+    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(rowb * (1 + G))) / 8));
+    hipError_t e = hipSuccess;
     for (int j0 = 0; j0 < a.nr; j0 += max_r) {
         const int nr = std::min(max_r, a.nr - j0);
-        const size_t lds = (size_t)nr * 8 + P * (1 + G);
+        const size_t lds = (size_t)nr * 8 + rowb * (1 + G);
         // the attribute belongs to the current device: set it for every launch that needs it
         if (lds > 64u * 1024u) {
-            e = hipFuncSetAttribute((const void*)corr_sx_kernel<CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            e = hipFuncSetAttribute((const void*)corr_sxb_kernel<MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds);
             if (e != hipSuccess) return e;
         }
         for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
-            hipLaunchKernelGGL((corr_sx_kernel<CB>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr, rho0, G,
-                               a.Cx + j0);
+            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr, rho0,
+                               G, a.Cx + j0);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
     }
-    const uint32_t nchunk = (uint32_t)((a.max_per_residue + kYChunk - 1) / kYChunk);
-    const uint32_t nband = (nb + kYRows - 1) / kYRows;
-    const uint32_t acw = sy_chunk();
-    const uint32_t nachunk = (nb + acw - 1) / acw;
-    if (nchunk == 0) return hipSuccess;
-    const uint32_t nsy = nchunk * nband * nachunk;
-    hipLaunchKernelGGL(corr_sy_kernel<CB>, dim3(128u * ((nsy + 7) / 8)), dim3(256), 0, s, g.plane0, L, a.zs, a.r,
-                       a.res_off, a.res_idx, nchunk, nband, nachunk, acw, a.Cy);
+    // along y: about 4 source-row words per thread, a grid row per 32 distances
+    const uint64_t pairs = (uint64_t)NS * tbits_words(L);
+    const uint32_t gyx = grid_cap((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((pairs + 1023) / 1024, 2048)));
+    const dim3 gy(gyx, (uint32_t)((a.nr + kYChunk - 1) / kYChunk));
+    hipLaunchKernelGGL((corr_syb_kernel<MODEL>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
+hipError_t launch_corr_sampled(const Geom& g, int model, const SampledArgs& a, hipStream_t s)
 {
     if (a.nr <= 0) return hipSuccess;
-    return g.cb == 1 ? corr_sampled<1>(g, a, s) : corr_sampled<4>(g, a, s);
+    return model == 2 ? corr_sampled<2>(g, a, s) : model == 1 ? corr_sampled<1>(g, a, s) : corr_sampled<0>(g, a, s);
 }
 
 }  // namespace mcl

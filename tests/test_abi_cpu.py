@@ -61,8 +61,9 @@ def test_query_bytes(mcl):
     assert mcl.query_bytes(mcl.ISING, 256) >= 256 * 256 // 2
     assert mcl.query_bytes(mcl.ISING, 2**17) >= 2**33
     for L in (64, 256, 2**16, 2**17):
-        # two 4-bit planes, then scratch: (L/16)^2 int8 sampled sources + O(L) sums
-        assert L * L // 2 <= mcl.query_bytes(mcl.BC, L) <= L * L // 2 + L * L // 256 + 64 * L + 8192
+        # two 4-bit planes, then scratch: the sampled columns as two bit planes
+        # (L^2 / 128 bytes each, at least 4 bytes a row) + O(L) sums
+        assert L * L // 2 <= mcl.query_bytes(mcl.BC, L) <= L * L // 2 + max(L * L // 64, 8 * L) + 64 * L + 8192
     with pytest.raises(mcl.MclError):
         mcl.query_bytes(mcl.ISING, 96 + 1)
     with pytest.raises(mcl.MclError):
@@ -73,8 +74,8 @@ def test_query_bytes(mcl):
 
 def test_query_bytes_one_bit(mcl):
     for L in (256, 768, 2**16, 2**17):
-        # two 1-bit planes, the scratch of the 4-bit layout, and the 32 KiB bucket table
-        assert L * L // 8 + 32768 <= mcl.query_bytes(mcl.ISING_LUT, L) <= L * L // 8 + L * L // 256 + 64 * L + 8192 + 32768
+        # two 1-bit planes, one bit plane of the sampled columns, O(L) sums and the 32 KiB bucket table
+        assert L * L // 8 + 32768 <= mcl.query_bytes(mcl.ISING_LUT, L) <= L * L // 8 + max(L * L // 128, 4 * L) + 64 * L + 8192 + 32768
     for L in (64, 128, 320):                    # a row of a 1-bit plane is whole 16-byte vectors
         with pytest.raises(mcl.MclError):
             mcl.query_bytes(mcl.ISING_LUT, L)

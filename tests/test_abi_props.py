@@ -71,5 +71,7 @@ def test_footprint_covers_the_planes(mcl, model, m):
         return
     bits = 1 if model == 2 else 4
     nb = mcl.query_bytes(model, L)
-    base = L * L * bits // 8 + (L // 16) ** 2          # both planes and the sampled-source copy
+    # both planes and the bits of the sampled columns (two bit planes for
+    # Blume-Capel), ceil(L / 512) words a row
+    base = L * L * bits // 8 + (2 if model == 1 else 1) * L * 4 * max(1, -(-L // 512))
     assert base <= nb <= base + 64 * L + 8192 + (32768 if model == 2 else 0)

@@ -8,11 +8,11 @@ histogram; B, M, Q and the spin counts).
   oracle's sums over that lattice.  At this size every measurement kernel
   runs the branches the 2^17 benchmark runs: workgroups with several tiles
   of the short-distance pass (reusing halo rows), several rows of the
-  sampled x pass and its unmasked loop, several source chunks of the sampled
-  y pass, several tasks per thread in the B/M/Q pass (4-bit cells).
+  sampled x pass with several words per lane, several distance chunks of
+  the sampled y pass, several tasks per thread in the B/M/Q pass (4-bit
+  cells) writing the sampled columns' bits.
 - The same branches at L <= 4096, forced by capping the grid of the
-  persistent kernels (MCL_MEASURE_GRID) and narrowing the y pass's source
-  chunks (MCL_SY_CHUNK), in protocol and full mode.
+  persistent kernels (MCL_MEASURE_GRID), in protocol and full mode.
 - t = 10^6: r_c(t) exceeds L/2, so every distance up to L/2 is measured and
   each residue class of the sampled distances spans several chunks.
 - The L = 256 quench of the parity-size workload in full: seed 1001,
@@ -90,11 +90,9 @@ def test_measure_parity_at_32768(mcl, model):
 @pytest.mark.parametrize("mode,L", [(2, 4096), (1, 512)])
 def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L):
     """Three workgroups for the persistent passes (so each takes several
-    tasks, tiles and source rows, with uneven shares) and source chunks of
-    100 columns (a ragged last chunk)."""
+    tasks, tiles, sampled rows and source-row words, with uneven shares)."""
     print("measure parity split launches", model, mode, L, flush=True)
     monkeypatch.setenv("MCL_MEASURE_GRID", "3")
-    monkeypatch.setenv("MCL_SY_CHUNK", "100" if L >= 4096 else "8")
     beta, D = _params(model)
     lat = mcl.Lattice(model, L, 4500 + model)
     lat.sweep(3, beta, D)
@@ -106,7 +104,6 @@ def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L):
     _compare(m, s, mode, _threads())
     # the knobs change the launch shape only
     monkeypatch.delenv("MCL_MEASURE_GRID")
-    monkeypatch.delenv("MCL_SY_CHUNK")
     m2 = lat.measure(mode)
     for k in ("B", "M", "Q", "counts", "sd"):
         assert m2[k] == m[k]
