@@ -205,12 +205,9 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v)
     return v;
 }
 
-__device__ __forceinline__ int wave_sum_i32(int v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// Sum over the active lanes of the wave, returned to every lane (the device
+// library's wavefront reduction: DPP row operations, no LDS permutes).
+__device__ __forceinline__ int wave_sum_i32(int v) { return __ockl_wfred_add_i32(v); }
 
 // Blume-Capel acceptance table entry: threshold and "always accept" flag
 // (dE <= 0), indexed ((n * 2) + b) * 9 + neighbour-cell-sum, n = s + 1.

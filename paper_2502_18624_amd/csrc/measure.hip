@@ -801,12 +801,30 @@ __global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restri
 }
 
 // Along y: S_y(r) = sum over the sampled rows b and words k of the pairs of
-// T row 16 b and T row 16 b + r (mod L).  Thread per (source row, word),
-// grid row per chunk of 32 distances; a thread keeps the source word and
-// the 32 distance sums in registers, the target words come from L2.
+// T row 16 b and T row 16 b + r (mod L).  Thread per (source row, group of
+// WPT words: 4 from L = 2048 on, read as one 16-byte load), grid row per
+// chunk of 32 distances; a thread keeps the source words and the 32
+// distance sums in registers, the target words come from L2.  Ising rows
+// from L = 512 on have no invalid bits: the sum is then 32 per word minus
+// twice the count of differing bits, which is all the loop counts.
 constexpr int kYChunk = 32;
 
-template <int MODEL>
+template <int WPT>
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ p, uint32_t (&w)[WPT])
+{
+    if (WPT == 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        w[0] = v.x;
+        w[WPT > 1 ? 1 : 0] = v.y;
+        w[WPT > 2 ? 2 : 0] = v.z;
+        w[WPT > 3 ? 3 : 0] = v.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) w[i] = p[i];
+    }
+}
+
+template <int MODEL, int WPT>
 __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restrict__ tb, uint32_t L,
                                                        const int32_t* __restrict__ rlist, int nr,
                                                        int64_t* __restrict__ Cy)
@@ -814,8 +832,10 @@ __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restric
     constexpr int NB = MODEL == 1 ? 2 : 1;
     const uint32_t NS = L >> 4;
     const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
-    const uint32_t nsw_log = 31 - __builtin_clz(NSW);
+    const uint32_t groups = NSW / WPT;                    // a power of two
+    const uint32_t g_log = 31 - __builtin_clz(groups);
     const bool full = L >= 512;
+    const bool diff_only = MODEL != 1 && full;
     const uint32_t valid = full ? 0xFFFFFFFFu : (NS >= 32 ? 0xFFFFFFFFu : ((1u << NS) - 1u));
     const size_t zoff = (size_t)L * NSW;                  // plane 1 (Blume-Capel nonzero bits)
     const int k0 = blockIdx.y * kYChunk;
@@ -827,19 +847,30 @@ __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restric
         rr[k] = k < kn ? (uint32_t)rlist[k0 + k] : 0u;
         acc[k] = 0;
     }
-    const uint32_t pairs = NS * NSW;
+    int words = 0;                                        // source words taken by this thread
+    const uint32_t pairs = NS * groups;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += gridDim.x * blockDim.x) {
-        const uint32_t b = p >> nsw_log, w = p & (NSW - 1);
+        const uint32_t b = p >> g_log, w = (p & (groups - 1)) * WPT;
         const uint32_t y = 16 * b;
-        const uint32_t s = tb[(size_t)y * NSW + w];
-        const uint32_t sz = NB == 2 ? tb[zoff + (size_t)y * NSW + w] : 0u;
+        uint32_t s[WPT], sz[WPT];
+        load_words<WPT>(tb + (size_t)y * NSW + w, s);
+        if (NB == 2) load_words<WPT>(tb + zoff + (size_t)y * NSW + w, sz);
+        words += WPT;
 #pragma unroll
         for (int k = 0; k < kYChunk; ++k) {
             if (k < kn) {
                 const uint32_t yp = (y + rr[k]) & (L - 1);
-                const uint32_t t = tb[(size_t)yp * NSW + w];
-                const uint32_t tz = NB == 2 ? tb[zoff + (size_t)yp * NSW + w] : 0u;
-                acc[k] += sampled_pairs<MODEL>(s, sz, t, tz, valid, full);
+                uint32_t t[WPT], tz[WPT];
+                load_words<WPT>(tb + (size_t)yp * NSW + w, t);
+                if (NB == 2) load_words<WPT>(tb + zoff + (size_t)yp * NSW + w, tz);
+#pragma unroll
+                for (int i = 0; i < WPT; ++i) {
+                    if (diff_only)
+                        acc[k] += (int)popc(s[i] ^ t[i]);
+                    else
+                        acc[k] += sampled_pairs<MODEL>(s[i], NB == 2 ? sz[i] : 0u, t[i], NB == 2 ? tz[i] : 0u, valid,
+                                                       full);
+                }
             }
         }
     }
@@ -847,7 +878,8 @@ __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restric
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kYChunk; ++k) {
-        const int s2 = wave_sum_i32(acc[k]);
+        const int v = diff_only ? 32 * words - 2 * acc[k] : acc[k];
+        const int s2 = wave_sum_i32(v);
         if ((threadIdx.x & 63) == 0) red[wave][k] = s2;
     }
     __syncthreads();
@@ -1002,11 +1034,16 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
     }
-    // along y: about 4 source-row words per thread, a grid row per 32 distances
-    const uint64_t pairs = (uint64_t)NS * tbits_words(L);
-    const uint32_t gyx = grid_cap((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((pairs + 1023) / 1024, 2048)));
+    // along y: a group of 4 source-row words per thread from L = 2048 on (one
+    // word below), a grid row per 32 distances
+    const uint32_t wpt = tbits_words(L) >= 4 ? 4u : 1u;
+    const uint64_t groups = (uint64_t)NS * (tbits_words(L) / wpt);
+    const uint32_t gyx = grid_cap((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((groups + 255) / 256, 2048)));
     const dim3 gy(gyx, (uint32_t)((a.nr + kYChunk - 1) / kYChunk));
-    hipLaunchKernelGGL((corr_syb_kernel<MODEL>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
+    if (wpt == 4)
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 4>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
+    else
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 1>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
     return hipGetLastError();
 }
 

@@ -87,12 +87,13 @@ def test_measure_parity_at_32768(mcl, model):
 
 
 @pytest.mark.parametrize("model", [0, 1, 2])
-@pytest.mark.parametrize("mode,L", [(2, 4096), (1, 512)])
-def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L):
-    """Three workgroups for the persistent passes (so each takes several
-    tasks, tiles, sampled rows and source-row words, with uneven shares)."""
-    print("measure parity split launches", model, mode, L, flush=True)
-    monkeypatch.setenv("MCL_MEASURE_GRID", "3")
+@pytest.mark.parametrize("mode,L,grid", [(2, 4096, 3), (2, 4096, 1), (1, 512, 3)])
+def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L, grid):
+    """Three workgroups (or one) for the persistent passes, so each takes
+    several tasks, tiles, sampled rows and groups of source-row words, with
+    uneven shares."""
+    print("measure parity split launches", model, mode, L, grid, flush=True)
+    monkeypatch.setenv("MCL_MEASURE_GRID", str(grid))
     beta, D = _params(model)
     lat = mcl.Lattice(model, L, 4500 + model)
     lat.sweep(3, beta, D)
