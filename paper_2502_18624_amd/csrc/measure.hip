@@ -41,13 +41,16 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 
 __device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n ? v - n : v; }
 
-// Per-word cell counts: +1 (n = 2), -1 (n = 0), 0 (n = 1), anything else.
+// Per-word cell counts: +1 (n = 2), -1 (n = 0), 0 (n = 1); anything else is
+// what they leave.  Bit 0 of each nibble carries the test; the mask of the
+// other bits is folded into `high`, so each count is one three-input
+// logic operation and one bit count.
 __device__ __forceinline__ void cell_counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
 {
-    const uint32_t b1 = w >> 1, high = (w >> 2) | (w >> 3);
-    np1 += popc((b1 & ~w & ~high) & 0x11111111u);
-    nm1 += popc(~(w | b1 | high) & 0x11111111u);
-    n0 += popc((w & ~(b1 | high)) & 0x11111111u);
+    const uint32_t b1 = w >> 1, high = (w >> 2) | (w >> 3) | 0xEEEEEEEEu;
+    np1 += popc(b1 & ~w & ~high);
+    nm1 += popc(~(w | b1 | high));
+    n0 += popc(w & ~(b1 | high));
 }
 
 // Sum of s * s' over the 8 cell pairs of two words, as (nonzero pairs,
@@ -197,22 +200,20 @@ __device__ __forceinline__ void sd_add1(uint32_t o, uint32_t a, uint32_t b, uint
     hist[4] += 32u - c8 - c0 - c6 - c2;
 }
 
-// 4-bit Ising cells (n in {0, 2}): per nibble the number d of neighbours
-// of the opposite sign, 0..4 (each xor nibble is 0 or 2, their sum at most
-// 8, and bit 0 of every nibble stays clear, so the shift moves nothing
-// across nibbles).  Adds the histogram of t = sigma h + 4 = 8 - 2 d and
-// returns the sum of d over the 8 cells.
-__device__ __forceinline__ uint32_t sd_add_ising4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                                  uint32_t (&hist)[9])
+// 4-bit Ising cells (n in {0, 2}): per nibble S = 2 d, d the number of
+// neighbours of the opposite sign, 0..4 (each xor nibble is 0 or 2, their
+// sum at most 8).  Adds the histogram of t = sigma h + 4 = 8 - 2 d for
+// d = 1 .. 4; d = 0 takes the rest of the cells, and the bond sum follows
+// from the histogram (both done once, at the end of the pass).
+__device__ __forceinline__ void sd_add_ising4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                              uint32_t (&hist)[9])
 {
-    const uint32_t D = ((a ^ o) + (b ^ o) + (c ^ o) + (d ^ o)) >> 1;
-    const uint32_t p0 = D & 0x11111111u, p1 = (D >> 1) & 0x11111111u, p2 = (D >> 2) & 0x11111111u;
-    hist[8] += popc(~(p0 | p1 | p2) & 0x11111111u);   // d = 0
-    hist[6] += popc(p0 & ~p1);                          // d = 1
-    hist[4] += popc(p1 & ~p0);                          // d = 2
-    hist[2] += popc(p0 & p1);                           // d = 3
-    hist[0] += popc(p2);                                // d = 4
-    return popc(p0) + 2u * popc(p1) + 4u * popc(p2);
+    const uint32_t S = xad(d, o, xad(c, o, xad(b, o, a ^ o)));
+    const uint32_t p = S >> 1, q = S >> 2, r = S >> 3;   // bits 0, 1, 2 of d at nibble bit 0, 1, 2
+    hist[6] += popc(p & ~q & 0x11111111u);               // d = 1 (d = 4 has bits 0 and 1 clear)
+    hist[4] += popc(q & ~p & 0x11111111u);               // d = 2
+    hist[2] += popc(p & q & 0x11111111u);                // d = 3
+    hist[0] += popc(r & 0x11111111u);                    // d = 4
 }
 
 // T bits (the sampled columns, see below) of row y from the thread's
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
     __shared__ int64_t red[4][14];
     const uint32_t Q = L >> C::kVecShift, W = L >> C::kWordShift;
     const uint32_t tasks = Q * (L / rows);
-    uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0;
+    uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0, cells = 0;
     uint32_t hist[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) hist[k] = 0;
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
         uint4 bup = b4[yu * Q], bmid = b4[(size_t)y0 * Q];
         const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;
         const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;
+        cells += 2 * C::kPerWord * 4 * rows;    // both planes, 4 words a row
         for (uint32_t r = 0; r < rows; ++r) {
             const uint32_t y = y0 + r;
             const size_t yd = (y + 1 == L) ? 0 : y + 1;
@@ -309,9 +311,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
                 C::counts(wa, np1, nm1, n0);
                 C::counts(wb, np1, nm1, n0);
                 if (MODEL == 0) {
-                    // every colour-0 cell carries 4 bonds: B = 4 N0 - 2 (misaligned pairs)
-                    nz += 32;
-                    diff += sd_add_ising4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
+                    sd_add_ising4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
                     sd_add_ising4(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
                     continue;
                 }
@@ -332,6 +332,16 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
             bup = bmid;
             bmid = bdn;
         }
+    }
+    if (MODEL == 0) {
+        // the thread's cells were 16 per word pair, the rest of the histogram
+        // has d = 0; each bond is seen from both ends, so the bond sum is
+        // 2 (cells) - sum of d over all cells
+        hist[8] = cells - hist[6] - hist[4] - hist[2] - hist[0];
+        nz = 2 * cells;
+        diff = 0;
+        const uint32_t dsum = hist[6] + 2 * hist[4] + 3 * hist[2] + 4 * hist[0];
+        nz -= dsum;
     }
     // acc: [0] B, [1] M, [2] #(+1), [3] #(-1), [4] #(0), [5 + k] #(sigma h = k - 4);
     // invalid cells are what the three counts leave of L^2 (done on the host)

@@ -344,3 +344,26 @@ def test_band_heights(mcl, model, L, rows):
             patch = oracle.window_run(model, L, seed, (x0 - pad) % L, (y0 - pad) % L, P, n, beta, D)
             assert np.array_equal(got, patch[pad:pad + W, pad:pad + W]), (x0, y0)
     lat.free()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_counts_report_cells_that_hold_no_spin(mcl, model):
+    """A packed lattice with some nibbles set to values no spin has (3 .. 15,
+    and 1, the Blume-Capel zero, in an Ising lattice): the +1 / 0 / -1
+    counts and the invalid count equal those of the cells as written."""
+    print("invalid cells", model, flush=True)
+    L = 512
+    lat = mcl.Lattice(model, L, 77 + model)
+    buf = lat.read_packed().copy()
+    rng = np.random.default_rng(5 + model)
+    pos = rng.choice(buf.size, size=300, replace=False)
+    vals = rng.integers(1, 16, size=(300, 2))
+    for p, (lo, hi) in zip(pos, vals):
+        buf[p] = (int(hi) << 4) | int(lo)
+    lat.write_packed(buf, 0)
+    m = lat.measure(mcl.CORR_NONE)
+    nib = np.concatenate([buf & 15, buf >> 4])
+    want = [int((nib == 0).sum()), int((nib == 1).sum()), int((nib == 2).sum())]
+    assert m["counts"] == want
+    assert m["invalid"] == int((nib > 2).sum()) > 0
+    assert sum(m["counts"]) + m["invalid"] == L * L
