@@ -484,7 +484,6 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
     const uint32_t t_begin = (uint32_t)((uint64_t)blockIdx.x * ntiles / gridDim.x);
     const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     constexpr uint32_t NB = ShortTile<MODEL>::NB;
-    constexpr uint32_t kRowElems = 2u * NB * (kSW + 1);   // elements of one tile row, both planes
     for (uint32_t tile = t_begin; tile < t_end; ++tile) {
         const uint32_t strip = tile / RT;
         const uint32_t rt = tile - strip * RT;
@@ -493,34 +492,37 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
         const bool reuse = tile != t_begin && rt != 0;
         __syncthreads();
         if (reuse) {
-            for (uint32_t idx = threadIdx.x; idx < kHalo * kRowElems; idx += blockDim.x) {
-                const uint32_t row = idx / kRowElems;
-                const uint32_t rem = idx - row * kRowElems;
-                const uint32_t c = rem / (NB * (kSW + 1));
-                const uint32_t rem2 = rem - c * (NB * (kSW + 1));
-                const uint32_t bp = rem2 / (kSW + 1);
-                const uint32_t col = rem2 - bp * (kSW + 1);
-                T.v[c][bp][row][col] = T.v[c][bp][row + kTH][col];
+            // rows kTH .. kTH + kHalo - 1 become rows 0 .. kHalo - 1, one
+            // (plane, bit plane) block of kTileRows x (kSW + 1) words at a time
+#pragma unroll
+            for (uint32_t blk = 0; blk < 2 * NB; ++blk) {
+                uint32_t* base = &T.v[blk / NB][blk % NB][0][0];
+                for (uint32_t o = threadIdx.x; o < kHalo * (kSW + 1); o += blockDim.x)
+                    base[o] = base[o + kTH * (kSW + 1)];
             }
             __syncthreads();
         }
         const uint32_t row0 = reuse ? (uint32_t)kHalo : 0u;
-        for (uint32_t idx = threadIdx.x; idx < 2u * (kTileRows - row0) * (kSW + 1); idx += blockDim.x) {
-            const uint32_t c = idx / ((kTileRows - row0) * (kSW + 1));
-            const uint32_t rem = idx - c * ((kTileRows - row0) * (kSW + 1));
-            const uint32_t row = row0 + rem / (kSW + 1);
-            const uint32_t col = rem % (kSW + 1);
-            uint32_t y = y0 + row;
-            while (y >= L) y -= L;
-            uint32_t qq = q0 + col;
-            while (qq >= Wp) qq -= Wp;
-            const size_t at = c * plane_units + (size_t)y * Wp + qq;
-            if (MODEL == 2) {
-                T.v[c][0][row][col] = planes[at];
-            } else {
-                const uint4 v = P4[at];
-                T.v[c][0][row][col] = nibble_bits<1>(v, false);            // n = 2: s = +1
-                if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+        const uint32_t nel = (kTileRows - row0) * (kSW + 1);     // new elements of a plane
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
+                const uint32_t rr = e / (kSW + 1);
+                const uint32_t col = e - rr * (kSW + 1);
+                const uint32_t row = row0 + rr;
+                // y0 + row < L + kTH; q0 + col < Wp + kSW + 1, which wraps once when Wp > kSW
+                uint32_t y = y0 + row;
+                if (y >= L) y -= L;
+                uint32_t qq = q0 + col;
+                if (qq >= Wp) qq = Wp > (uint32_t)kSW ? qq - Wp : qq % Wp;
+                const size_t at = c * plane_units + (size_t)y * Wp + qq;
+                if (MODEL == 2) {
+                    T.v[c][0][row][col] = planes[at];
+                } else {
+                    const uint4 v = P4[at];
+                    T.v[c][0][row][col] = nibble_bits<1>(v, false);            // n = 2: s = +1
+                    if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+                }
             }
         }
         __syncthreads();
