@@ -918,9 +918,6 @@ hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-// Persistent kernels use at most this many workgroups (a few per CU).
-constexpr uint32_t kMaxGrid = 2048;
-
 // Optional cap on the workgroups of the persistent measurement kernels
 // (B/M/Q pass, short-distance tiles, sampled x rows): the environment
 // variable MCL_MEASURE_GRID, read at every launch.  It changes how the work
@@ -937,14 +934,14 @@ uint32_t grid_cap(uint32_t want)
 
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s)
 {
-    // bands of 16 to 64 rows: as tall as leaves a full persistent grid
-    // (kMaxGrid workgroups of 256 threads) with one task per thread or more;
-    // a band re-reads two halo rows, so taller bands read less
-    int64_t want = 16;
-    while (want < 64 && g.Q * (g.L / (2 * want)) >= (int64_t)kMaxGrid * 256) want *= 2;
-    const int64_t rows = pick_rows(g.L, want);
+    // one thread per task, bands of 32 rows.  Measured at L = 2^17 (4-bit
+    // Ising): 1.88 ms and 1.39x the lattice's bytes read, against 2.07 ms and
+    // 1.32x for 16-row bands in a persistent grid of 2048 workgroups, and
+    // 2.35 ms and 1.50x for 64-row bands there (longer walks read the halo
+    // lines shared with neighbouring waves more often from HBM)
+    const int64_t rows = pick_rows(g.L, 32);
     const int64_t threads = g.Q * (g.L / rows);
-    const uint32_t grid = grid_cap((uint32_t)std::min<int64_t>((threads + 255) / 256, kMaxGrid));
+    const uint32_t grid = grid_cap((uint32_t)((threads + 255) / 256));
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
     // the pass writes the T bits from L = 512 on; below, a kernel of its own
     uint32_t* tb = g.L >= 512 ? tbits : nullptr;

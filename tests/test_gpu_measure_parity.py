@@ -9,10 +9,11 @@ histogram; B, M, Q and the spin counts).
   runs the branches the 2^17 benchmark runs: workgroups with several tiles
   of the short-distance pass (reusing halo rows), several rows of the
   sampled x pass with several words per lane, several distance chunks of
-  the sampled y pass, several tasks per thread in the B/M/Q pass (4-bit
-  cells) writing the sampled columns' bits.
+  the sampled y pass, and the B/M/Q pass writing the sampled columns'
+  bits.
 - The same branches at L <= 4096, forced by capping the grid of the
-  persistent kernels (MCL_MEASURE_GRID), in protocol and full mode.
+  measurement kernels (MCL_MEASURE_GRID), in protocol and full mode, with
+  several B/M/Q tasks per thread besides.
 - t = 10^6: r_c(t) exceeds L/2, so every distance up to L/2 is measured and
   each residue class of the sampled distances spans several chunks.
 - The L = 256 quench of the parity-size workload in full: seed 1001,
