@@ -184,10 +184,11 @@ def traffic_source():
         sha, state)
 
 
-def measured_valu_busy(name):
-    """Fraction of SIMD cycles issuing VALU instructions (PMC), or None."""
+def measured_valu_util(name):
+    """VALU lane-instructions of a launch over its duration, as a fraction of
+    the chip's issue peak (PMC and kernel trace), or None."""
     k = profile_record(name)
-    return None if k is None or "valu_busy" not in k else round(k["valu_busy"], 3)
+    return None if k is None or "valu_util" not in k else round(k["valu_util"], 3)
 
 
 def _calibrate(mode):
@@ -279,7 +280,7 @@ def quench_leg(model, L, seed, beta, D, n, half_bytes, blocks_per_update, label,
            "hbm_frac": round(half_bytes / half_s / 1e9 / HBM_PEAK_GBS, 4),
            "philox_frac": round(gblocks / PHILOX_PEAK_GBLOCKS, 4),
            "hbm_traffic_bytes_per_launch": measured_traffic(traffic_key),
-           "valu_busy_pmc": measured_valu_busy(traffic_key),
+           "valu_util_pmc": measured_valu_util(traffic_key),
            "algorithmic_bytes_per_launch": half_bytes,
            "measure_share": round(t_meas / wall, 4),
            "final": {"t": out["t"], "B": out["B"], "M": out["M"], "Q": out["Q"],
@@ -555,7 +556,7 @@ def run(args):
                      "work_per_launch": "%d Philox4x32-10 blocks (one u32 draw per update), %d bytes" % (
                          int(half_updates / 4), int(half_bytes)),
                      "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                     "valu_busy_pmc": measured_valu_busy("ising_4bit") if L == 2 ** 17 else None,
+                     "valu_util_pmc": measured_valu_util("ising_4bit") if L == 2 ** 17 else None,
                      "philox_alone_Gblocks": philox_alone,
                      "frac_of_philox_alone": round(blocks_gps / philox_alone, 4) if philox_alone else None},
         "paper_context": {"updates_per_ns": 1797, "hardware": "1x GB200, 1-bit cells with LUT random bits",

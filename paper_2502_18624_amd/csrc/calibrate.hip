@@ -9,7 +9,8 @@
 //             counter words as the sweep's accept draws use them: a per-lane
 //             block index, zero high word, wave-uniform t and colour), and
 //             for comparison separate high/low multiplies with plain xors;
-//   alu/mad : 32-bit integer VALU issue rate and v_mad_u64_u32 rate.
+//   alu/mad : 32-bit integer VALU issue rate (lane-instructions/s) and the
+//             v_mad_u64_u32 rate (full rate on gfx950).
 // Usage: mcl_calibrate [copy|philox]   (with an argument only that test runs)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -206,14 +207,18 @@ int main(int argc, char** argv)
         for (int rep = 0; rep < 2; ++rep) {
             const int iters = 256;
             const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(alu_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u); });
-            const double ops = (double)threads * iters * 16 * 8 * 2;
-            printf("alu xor+add: %.3f ms  %.2f Tops/s (lane ops)\n", ms, ops / ms / 1e9);
+            // each xor-then-add is one v_xad_u32: one lane-instruction per step
+            const double insts = (double)threads * iters * 16 * 8;
+            printf("alu v_xad: %.3f ms  %.2f T lane-instructions/s (%.3f of 39.32e12)\n", ms, insts / ms / 1e9,
+                   insts / ms / 1e9 / 39.3216);
         }
         for (int rep = 0; rep < 2; ++rep) {
             const int iters = 64;
             const float ms = timed(e0, e1, [&] { hipLaunchKernelGGL(mad_kernel, dim3(threads / 256), dim3(256), 0, 0, out, iters, 3u); });
+            // each step is one v_mad_u64_u32 and one xor: two lane-instructions
             const double ops = (double)threads * iters * 16 * 8;
-            printf("mad_u64 (+1 xor each): %.3f ms  %.2f T mads/s\n", ms, ops / ms / 1e9);
+            printf("mad_u64 (+1 xor each): %.3f ms  %.2f T mads/s (%.3f of the issue peak with the xors)\n", ms,
+                   ops / ms / 1e9, 2 * ops / ms / 1e9 / 39.3216);
         }
     }
     CHECK(hipFree(out));

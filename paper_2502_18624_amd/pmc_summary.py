@@ -1,14 +1,20 @@
-"""Summarise rocprofv3 PMC runs of the benchmark into HBM bytes per launch.
+"""Summarise rocprofv3 PMC runs of the benchmark into HBM bytes per launch
+and VALU figures per sweep kernel.
 
 FETCH_SIZE and WRITE_SIZE are scaled by what the same counters read for the
 calibration copy kernel, which moves a known 4 GiB in and 4 GiB out per
-dispatch.  Usage (from the repository root, after the four PMC runs):
+dispatch.  VALU utilisation is the kernel's VALU lane-instructions
+(SQ_INSTS_VALU x 64) over its average launch duration from a kernel trace
+of the same command, against the issue peak of the chip (256 CUs x 4 SIMDs
+x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s); it cannot exceed 1.
+Usage (from the repository root, after the runs):
 
-    python -m paper_2502_18624_amd.pmc_summary <dir with fetch/ write/ cfetch/ cwrite/> [<dir with valu/>]
+    python -m paper_2502_18624_amd.pmc_summary <dir with fetch/ write/ cfetch/ cwrite/> [<dir with valu/> [<kernel_stats.csv>]]
 
-The optional second directory holds a run with the VALU and LDS counters
+The second directory holds a run with the VALU and LDS counters
 (SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAVES
-SQ_BUSY_CYCLES GRBM_GUI_ACTIVE).
+SQ_BUSY_CYCLES GRBM_GUI_ACTIVE); the kernel-stats file is the
+rocprofv3 --kernel-trace --stats summary of the same command.
 """
 from __future__ import annotations
 
@@ -68,9 +74,22 @@ def per_kernel_counters(path):
     return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in d.items()}
 
 
-def valu_summary(path):
+VALU_PEAK_LANE_INSTS = N_SIMD * 16 * 2.4e9
+
+
+def kernel_durations(stats_csv):
+    """Average launch duration (seconds) per shortened kernel name from a
+    rocprofv3 --stats kernel_stats.csv."""
+    out = {}
+    for r in csv.DictReader(open(stats_csv)):
+        out[short(r["Name"])] = float(r["AverageNs"]) * 1e-9
+    return out
+
+
+def valu_summary(path, durations=None):
     """VALU issue and LDS figures per sweep kernel from a run with SQ_INSTS_VALU,
-    SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES and GRBM_GUI_ACTIVE."""
+    SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES and GRBM_GUI_ACTIVE; with the
+    launch durations of a kernel trace, also the VALU utilisation."""
     c = per_kernel_counters(path)
     out = {}
     for name, (prefix, L, bits) in SWEEP_KERNELS.items():
@@ -82,15 +101,20 @@ def valu_summary(path):
         updates = L * L / 2
         out[name] = {"valu_wave_insts_per_launch": m["SQ_INSTS_VALU"],
                      "valu_lane_ops_per_update": m["SQ_INSTS_VALU"] * 64 / updates,
-                     "valu_busy": m["SQ_INSTS_VALU"] * 4 / (N_SIMD * cycles),
                      "gpu_cycles_per_launch": cycles,
                      "lds_insts_per_launch": m["SQ_INSTS_LDS"],
                      "lds_bank_conflict_share": m["SQ_LDS_BANK_CONFLICT"] / N_CU / cycles,
                      "waves": m["SQ_WAVES"]}
+        if durations:
+            ds = [durations[k] for k in ks if k in durations]
+            if ds:
+                dur = sum(ds) / len(ds)
+                out[name]["avg_launch_s"] = dur
+                out[name]["valu_util"] = m["SQ_INSTS_VALU"] * 64 / (dur * VALU_PEAK_LANE_INSTS)
     return out
 
 
-def main(d, valu_dir=None):
+def main(d, valu_dir=None, stats_csv=None):
     f = per_kernel(os.path.join(d, "fetch", "bench_counter_collection.csv"))
     w = per_kernel(os.path.join(d, "write", "bench_counter_collection.csv"))
     cf = per_kernel(os.path.join(d, "cfetch", "copy_counter_collection.csv"))
@@ -109,11 +133,14 @@ def main(d, valu_dir=None):
                          "hbm_write_bytes_per_launch": write, "hbm_bytes_per_launch": fetch + write,
                          "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": (fetch + write) / alg}
     if valu_dir:
-        for name, v in valu_summary(os.path.join(valu_dir, "valu", "bench_counter_collection.csv")).items():
+        durations = kernel_durations(stats_csv) if stats_csv else None
+        for name, v in valu_summary(os.path.join(valu_dir, "valu", "bench_counter_collection.csv"),
+                                    durations).items():
             kernels.setdefault(name, {}).update(v)
     return {"kernel_source_sha": source_sha(), "fetch_scale": fs, "write_scale": ws, "sweep_kernels": kernels,
             "per_kernel_bytes": {k: [f[k] * fs * 1024, w.get(k, 0.0) * ws * 1024] for k in f}}
 
 
 if __name__ == "__main__":
-    print(json.dumps(main(sys.argv[1], sys.argv[2] if len(sys.argv) > 2 else None), indent=1))
+    print(json.dumps(main(sys.argv[1], sys.argv[2] if len(sys.argv) > 2 else None,
+                          sys.argv[3] if len(sys.argv) > 3 else None), indent=1))

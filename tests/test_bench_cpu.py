@@ -41,7 +41,7 @@ def _fake_tree(tmp_path, sha_matches):
         p.write_text("// %s\n" % f)
     (tmp_path / "profiles").mkdir()
     rec = {"kernel_source_sha": "0" * 16,
-           "sweep_kernels": {"ising_4bit": {"hbm_bytes_per_launch": 13.55e9, "valu_busy": 0.9978}}}
+           "sweep_kernels": {"ising_4bit": {"hbm_bytes_per_launch": 13.55e9, "valu_util": 0.9978}}}
     if sha_matches:
         old = bench.ROOT
         bench.ROOT = str(tmp_path)
@@ -58,11 +58,11 @@ def test_pmc_record_only_for_the_kernel_source_it_was_taken_on(tmp_path, monkeyp
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     if current:
         assert bench.measured_traffic("ising_4bit") == 13550000000
-        assert bench.measured_valu_busy("ising_4bit") == 0.998
+        assert bench.measured_valu_util("ising_4bit") == 0.998
         assert bench.traffic_source().endswith("current")
     else:
         assert bench.measured_traffic("ising_4bit") is None
-        assert bench.measured_valu_busy("ising_4bit") is None
+        assert bench.measured_valu_util("ising_4bit") is None
         assert "stale" in bench.traffic_source()
     assert bench.measured_traffic("no_such_kernel") is None
 

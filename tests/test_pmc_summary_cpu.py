@@ -67,7 +67,22 @@ def test_valu_figures(tmp_path):
                  (ISING % c, "GRBM_GUI_ACTIVE", 8 * cycles)]
     _write(tmp_path / "valu" / "bench_counter_collection.csv", rows)
     v = pmc_summary.valu_summary(str(tmp_path / "valu" / "bench_counter_collection.csv"))["ising_4bit"]
-    assert v["valu_busy"] == pytest.approx(0.9)
+    assert "valu_util" not in v                   # no launch durations given
+    durations = {"half_sweep_kernel<0, true, 0>": 3.4e-3, "half_sweep_kernel<0, true, 1>": 3.4e-3}
+    v = pmc_summary.valu_summary(str(tmp_path / "valu" / "bench_counter_collection.csv"), durations)["ising_4bit"]
+    # 90% of 1024 SIMDs x 2.4 GHz issuing one wave64 instruction per 4 cycles
+    assert v["valu_util"] == pytest.approx(0.9)
+    assert v["avg_launch_s"] == pytest.approx(3.4e-3)
     assert v["gpu_cycles_per_launch"] == pytest.approx(cycles)
     assert v["valu_lane_ops_per_update"] == pytest.approx(insts * 64 / updates)
     assert v["lds_bank_conflict_share"] == pytest.approx(0.25)
+
+
+def test_kernel_durations_from_stats(tmp_path):
+    path = tmp_path / "bench_kernel_stats.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs"])
+        w.writeheader()
+        w.writerow({"Name": ISING % 0, "Calls": 2, "TotalDurationNs": 7.0e6, "AverageNs": 3.5e6})
+    d = pmc_summary.kernel_durations(str(path))
+    assert d == {"half_sweep_kernel<0, true, 0>": pytest.approx(3.5e-3)}
