@@ -58,8 +58,11 @@ __device__ __forceinline__ uint32_t model_of(uint32_t m)
     return MASK == kMaskIsing ? 0u : MASK == kMaskBC ? 1u : MASK == kMaskLut ? 2u : m;
 }
 
+// At most 128 VGPRs (4 waves per SIMD): the launches that hold Ising and
+// Blume-Capel replicas together would otherwise take 131 and run 3 waves;
+// the few values this spills are kept across a tile, not inside its rows.
 template <int MASK, int COLOR>
-__global__ __launch_bounds__(256) void group_half_kernel(const GroupDesc* __restrict__ desc, int count,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void group_half_kernel(const GroupDesc* __restrict__ desc, int count,
                                                          const uint2* __restrict__ bc_tables,
                                                          const LutRec* __restrict__ luts, uint32_t total,
                                                          uint32_t s, const uint32_t* __restrict__ sbase)

@@ -74,6 +74,11 @@ __global__ __launch_bounds__(256) void half_sweep_kernel(uint32_t* __restrict__ 
     const uint32_t band = g / Q;
     const uint32_t y0 = band * rows;
     if (y0 >= L) return;
+    // a row of a whole number of waves: the wave's row terms are scalar
+    if ((Q & 63u) == 0u) {
+        dev::band_update_wave<MODEL, HI0, COLOR>(own, oth, L, rows, q, y0, t, k0, k1, T4, T8, s_tab.e);
+        return;
+    }
     // blocks of the band: accept draws of in-colour cells y0 L/2 + 32 q .. (y0 + rows - 1) L/2 + 32 q + 31
     uint32_t hu;
     const int hm = dev::counter_mode(HI0, ((uint64_t)y0 * (L >> 1) + 32u * q) >> 2,

@@ -46,16 +46,20 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 // (acc = acc + acc + carry) and lets word d read its cells' bits at nibble
 // bit 0 as (mask >> d) & 0x11111111.
 // ---------------------------------------------------------------------------
+// The block index is cb + blk0 + k (k = 0..7) with cb wave-uniform (0 on
+// the per-lane walk).
 template <int HM>
-__device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t color, uint32_t k0, uint32_t k1,
-                                             uint32_t hu, uint32_t T4, uint32_t T8, uint32_t& m4, uint32_t& m8)
+__device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t cb, uint32_t t, uint32_t color, uint32_t k0,
+                                             uint32_t k1, uint32_t hu, uint32_t T4, uint32_t T8, uint32_t& m4,
+                                             uint32_t& m8)
 {
     uint32_t a4 = 0, a8 = 0;
-    // the low counter words of the vector's 8 blocks are lo32(blk0) + k
+    // the low counter words of the vector's 8 blocks are cb + lo32(blk0) + k
     // without a wrap unless the high word varies per lane (HM 2), so the first
-    // round's product M0 (lo32(blk0) + k) is one multiply-add with the
-    // constant M0 k
+    // round's product M0 (cb + lo32(blk0) + k) is one multiply-add with the
+    // uniform addend M0 cb + M0 k
     const uint32_t c0 = lo32(blk0);
+    const uint64_t mb = (uint64_t)kPhiloxM0 * cb;
 #pragma unroll
     for (int h = 1; h >= 0; --h) {
         Philox4 P[4];
@@ -65,8 +69,8 @@ __device__ __forceinline__ void accept_masks(uint64_t blk0, uint32_t t, uint32_t
             if (HM == 2)
                 P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
             else
-                P[d] = philox4x32_10_p0(mad_m0(c0, (uint64_t)kPhiloxM0 * (uint32_t)(2 * d + h)), hiw<HM>(b, hu), t,
-                                        color, k0, k1);
+                P[d] = philox4x32_10_p0(mad_m0(c0, mb + (uint64_t)kPhiloxM0 * (uint32_t)(2 * d + h)),
+                                        hiw<HM>(b, hu), t, color, k0, k1);
         }
 #pragma unroll
         for (int jj = 3; jj >= 0; --jj)
@@ -114,11 +118,12 @@ __device__ __forceinline__ uint32_t to_bit1(uint32_t m)
 
 template <int HM>
 __device__ __forceinline__ uint4 ising_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
-                                           uint32_t halo, bool odd, uint64_t blk0, uint32_t t, uint32_t color,
-                                           uint32_t k0, uint32_t k1, uint32_t hu, uint32_t T4, uint32_t T8)
+                                           uint32_t halo, bool odd, uint64_t blk0, uint32_t cb, uint32_t t,
+                                           uint32_t color, uint32_t k0, uint32_t k1, uint32_t hu, uint32_t T4,
+                                           uint32_t T8)
 {
     uint32_t m4, m8;
-    accept_masks<HM>(blk0, t, color, k0, k1, hu, T4, T8, m4, m8);
+    accept_masks<HM>(blk0, cb, t, color, k0, k1, hu, T4, T8, m4, m8);
     uint32_t res[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -200,8 +205,8 @@ __device__ __forceinline__ void load_bc_table(BCLds& lds, const uint2* __restric
 
 template <int HM>
 __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const uint4& dn, const uint4& mid,
-                                        uint32_t halo, bool odd, uint64_t blk0, uint32_t pbits, uint32_t t,
-                                        uint32_t color, uint32_t k0, uint32_t k1, uint32_t hu,
+                                        uint32_t halo, bool odd, uint64_t blk0, uint32_t cb, uint32_t pbits,
+                                        uint32_t t, uint32_t color, uint32_t k0, uint32_t k1, uint32_t hu,
                                         const uint2* __restrict__ tab)
 {
     uint32_t ev[4], od[4], nxt[4];
@@ -218,14 +223,20 @@ __device__ __forceinline__ uint4 bc_vec(const uint4& src, const uint4& up, const
         nxt[d] = v - shl_or<1>(ge3, ge3);                     // mod 3
     }
     // nacc = -(accept bits), shifted in cell by cell: 2 (-a) - bit = -(2 a + bit)
+    // block indices cb + blk0 + k as in accept_masks
     uint32_t nacc = 0;
+    const uint64_t mb = (uint64_t)kPhiloxM0 * cb;
 #pragma unroll
     for (int h = 1; h >= 0; --h) {
         Philox4 P[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const uint64_t b = blk0 + 2 * d + h;
-            P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
+            if (HM == 2)
+                P[d] = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, color, k0, k1);
+            else
+                P[d] = philox4x32_10_p0(mad_m0(lo32(blk0), mb + (uint64_t)kPhiloxM0 * (uint32_t)(2 * d + h)),
+                                        hiw<HM>(b, hu), t, color, k0, k1);
         }
 #pragma unroll
         for (int jj = 3; jj >= 0; --jj)
@@ -277,12 +288,12 @@ __device__ __forceinline__ void row_step(RowState& st, const uint4* __restrict__
     const uint32_t halo = st.hrow[ODD ? hwr : hwl];
     uint4 res;
     if (MODEL == 0) {
-        res = ising_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, t, color, k0, k1, hu, T4, T8);
+        res = ising_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, 0u, t, color, k0, k1, hu, T4, T8);
     } else {
         const uint64_t pb = st.kv >> 7;
         const Philox4 p = philox4x32_10(lo32(pb), HM == 0 ? 0u : hi32(pb), t, 2u + color, k0, k1);
         const uint32_t pbits = philox_word(p, (int)((st.kv >> 5) & 3));
-        res = bc_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, pbits, t, color, k0, k1, hu, tab);
+        res = bc_vec<HM>(src, st.up, dn, st.mid, halo, ODD, st.blk, 0u, pbits, t, color, k0, k1, hu, tab);
     }
     *st.pown = res;
     st.up = st.mid;
@@ -322,6 +333,90 @@ __device__ __forceinline__ void band_update(uint32_t* __restrict__ own, const ui
 }
 
 // ---------------------------------------------------------------------------
+// The same walk for a wave whose 64 lanes hold 64 consecutive column vectors
+// of one band (L a multiple of 4096, so a row holds a whole number of waves):
+// the row, its addresses, the periodic wrap in y and the Philox counters'
+// row terms are wave-uniform and stay in scalar registers, and a lane keeps
+// only its byte offsets in a row and its counter offsets from the wave's
+// first block.  The wave's accept blocks of a row are the 512 indices from
+// y L/8 + 8 q0 (q0 = q rounded down to 64, a multiple of 512 since L/8 is),
+// so cb + 8 (q - q0) + k never carries into the high word, which is one
+// value per wave and row; its proposal blocks (Blume-Capel) are the 16
+// indices from y L/256 + q0/4, likewise aligned.
+// ---------------------------------------------------------------------------
+struct WaveLane {
+    uint32_t qo;        // byte offset of the lane's vector in a row
+    uint32_t hl, hr;    // byte offsets of the words left and right of it
+    uint32_t a8;        // 8 (q - q0): accept-block offset in the wave's row
+    uint32_t p4;        // (q - q0) / 4: proposal-block offset
+    uint32_t sel;       // q & 3: the proposal block's output word
+};
+
+__device__ __forceinline__ uint4 load_row(const char* row, uint32_t off)
+{
+    return *reinterpret_cast<const uint4*>(row + off);
+}
+
+template <int MODEL, bool HI0, bool ODD>
+__device__ __forceinline__ void row_step_wave(const WaveLane& w, const char* oth, char* own, uint32_t y, uint32_t L,
+                                              uint32_t q0, uint4& up, uint4& mid, uint32_t color, uint32_t t,
+                                              uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8, const uint2* tab)
+{
+    const uint64_t rowb = L >> 2;                       // bytes per row of a plane
+    // keep the lane offsets' widening next to each access, where it forms
+    // the scalar-base + 32-bit-offset address of global loads and stores
+    uint32_t qo = w.qo, ho = ODD ? w.hr : w.hl;
+    asm volatile("" : "+v"(qo), "+v"(ho));
+    const char* orow = oth + (uint64_t)y * rowb;
+    const char* odn = (y + 1 == L) ? oth : orow + rowb;
+    char* wrow = own + (uint64_t)y * rowb;
+    const uint4 dn = load_row(odn, qo);
+    const uint4 src = load_row(wrow, qo);
+    const uint32_t halo = *reinterpret_cast<const uint32_t*>(orow + ho);
+    const uint64_t bw = (uint64_t)y * (L >> 3) + 8u * q0;
+    constexpr int HM = HI0 ? 0 : 1;
+    uint4 res;
+    if (MODEL == 0) {
+        res = ising_vec<HM>(src, up, dn, mid, halo, ODD, w.a8, lo32(bw), t, color, k0, k1, hi32(bw), T4, T8);
+    } else {
+        const uint64_t pw = (uint64_t)y * (L >> 8) + (q0 >> 2);
+        const Philox4 p = philox4x32_10_p0(mad_m0(w.p4, (uint64_t)kPhiloxM0 * lo32(pw)), HI0 ? 0u : hi32(pw), t,
+                                           2u + color, k0, k1);
+        const uint32_t pbits = philox_word(p, (int)w.sel);
+        res = bc_vec<HM>(src, up, dn, mid, halo, ODD, w.a8, lo32(bw), pbits, t, color, k0, k1, hi32(bw), tab);
+    }
+    *reinterpret_cast<uint4*>(wrow + qo) = res;
+    up = mid;
+    mid = dn;
+}
+
+template <int MODEL, bool HI0, int COLOR>
+__device__ __forceinline__ void band_update_wave(uint32_t* __restrict__ own, const uint32_t* __restrict__ oth,
+                                                 uint32_t L, uint32_t rows, uint32_t q, uint32_t y0, uint32_t t,
+                                                 uint32_t k0, uint32_t k1, uint32_t T4, uint32_t T8, const uint2* tab)
+{
+    const uint32_t W = L >> 4;
+    const uint32_t q0 = __builtin_amdgcn_readfirstlane(q & ~63u);
+    y0 = __builtin_amdgcn_readfirstlane(y0);
+    WaveLane w;
+    w.qo = q << 4;
+    w.hl = ((q == 0) ? W - 1 : 4 * q - 1) << 2;
+    w.hr = ((4 * q + 4 == W) ? 0 : 4 * q + 4) << 2;
+    w.a8 = (q & 63u) << 3;
+    w.p4 = (q & 63u) >> 2;
+    w.sel = q & 3u;
+    const char* ob = reinterpret_cast<const char*>(oth);
+    char* wb = reinterpret_cast<char*>(own);
+    const uint64_t rowb = L >> 2;
+    uint4 up = load_row(ob + (uint64_t)(y0 == 0 ? L - 1 : y0 - 1) * rowb, w.qo);
+    uint4 mid = load_row(ob + (uint64_t)y0 * rowb, w.qo);
+    for (uint32_t r = 0; r < rows; r += 2) {
+        row_step_wave<MODEL, HI0, COLOR == 1>(w, ob, wb, y0 + r, L, q0, up, mid, COLOR, t, k0, k1, T4, T8, tab);
+        row_step_wave<MODEL, HI0, COLOR == 0>(w, ob, wb, y0 + r + 1, L, q0, up, mid, COLOR, t, k0, k1, T4, T8, tab);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 1-bit Ising with table-driven random bits (section 3.2).  Cells are single
 // bits (1 for s = +1), 32 per word, 128 per 16-byte vector.  For a word of
 // 32 cells:
@@ -344,20 +439,15 @@ __device__ __forceinline__ uint32_t lut_lookup(const uint32_t* __restrict__ T, u
     return k < kmax ? k : kmax;
 }
 
-// Random bits of the 32 cells whose 8 groups of 4 start at group g0 (a
-// multiple of 8): Philox blocks g0/4 and g0/4 + 1 of `stream`.
-template <int HM>
-__device__ __forceinline__ uint32_t lut_word(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
-                                             uint32_t hu, const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
+// Random bits of 32 cells (8 groups of 4) from the 8 draws of two Philox
+// blocks P, R, by the exact table search.
+__device__ __forceinline__ uint32_t lut_word(const Philox4& P, const Philox4& R, const uint32_t* __restrict__ T,
+                                             uint32_t T8, uint32_t kmax)
 {
     uint32_t w = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint64_t b = (g0 >> 2) + h;
-        const Philox4 P = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, stream, k0, k1);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w |= lut_lookup(T, T8, kmax, philox_word(P, j)) << (4 * (4 * h + j));
-    }
+    for (int j = 0; j < 8; ++j)
+        w |= lut_lookup(T, T8, kmax, philox_word(j < 4 ? P : R, j & 3)) << (4 * j);
     return w;
 }
 
@@ -390,26 +480,38 @@ __device__ __forceinline__ uint64_t lut_bucket_addend(const uint32_t* T, uint32_
     return uint64_t(1) << 63;                                                   // exact search
 }
 
+// Pattern of draw i (0..7) of a word: bits 4i .. 4i + 3, placed with one
+// v_lshl_or_b32 (a pattern is at most 15 on the fast path; a marked bucket
+// sets bit 31 of k, which `flags` collects).
+template <int I>
+__device__ __forceinline__ void lut_fast_draw(uint32_t u, const uint2* __restrict__ B, uint32_t& w, uint32_t& flags)
+{
+    const uint2 e = B[u >> 20];
+    const uint32_t k = add_hi(u, ((uint64_t)e.y << 32) | e.x);
+    flags |= k;
+    w = shl_or<4 * I>(k, w);
+}
+
+// Random bits of the 32 cells whose 8 groups of 4 start at group g0 (a
+// multiple of 8): Philox blocks g0/4 and g0/4 + 1 of `stream`.
 template <int HM>
 __device__ __forceinline__ uint32_t lut_word_fast(uint64_t g0, uint32_t t, uint32_t stream, uint32_t k0, uint32_t k1,
                                                   uint32_t hu, const uint2* __restrict__ B,
                                                   const uint32_t* __restrict__ T, uint32_t T8, uint32_t kmax)
 {
     uint32_t w = 0, flags = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint64_t b = (g0 >> 2) + h;
-        const Philox4 P = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, stream, k0, k1);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t u = philox_word(P, j);
-            const uint2 e = B[u >> 20];
-            const uint32_t k = add_hi(u, ((uint64_t)e.y << 32) | e.x);
-            flags |= k;
-            w |= k << (4 * (4 * h + j));
-        }
-    }
-    if (flags >> 31) w = lut_word<HM>(g0, t, stream, k0, k1, hu, T, T8, kmax);
+    const uint64_t b = g0 >> 2;
+    const Philox4 P = philox4x32_10(lo32(b), hiw<HM>(b, hu), t, stream, k0, k1);
+    const Philox4 R = philox4x32_10(lo32(b + 1), hiw<HM>(b + 1, hu), t, stream, k0, k1);
+    lut_fast_draw<0>(P.v0, B, w, flags);
+    lut_fast_draw<1>(P.v1, B, w, flags);
+    lut_fast_draw<2>(P.v2, B, w, flags);
+    lut_fast_draw<3>(P.v3, B, w, flags);
+    lut_fast_draw<4>(R.v0, B, w, flags);
+    lut_fast_draw<5>(R.v1, B, w, flags);
+    lut_fast_draw<6>(R.v2, B, w, flags);
+    lut_fast_draw<7>(R.v3, B, w, flags);
+    if (flags >> 31) w = lut_word(P, R, T, T8, kmax);
     return w;
 }
 
