@@ -289,8 +289,10 @@ int compute_units(int dev)
 }
 
 // The launches of one batched call and the device image they read:
-// descriptors (launch by launch), Blume-Capel tables, 1-bit records and the
-// word a captured graph adds its sweep offset to.
+// descriptors (launch by launch), Blume-Capel tables, 1-bit records, and a
+// 256-byte block holding the word a captured graph adds its sweep offset to
+// (word 0) and the tile-claim counters of persistent launches (words 16 to
+// 31), all uploaded as zero.
 struct GroupLaunch {
     int mask;          // models in the launch (kMask*)
     size_t first;      // its first descriptor
@@ -329,6 +331,8 @@ int group_layout(mcl_lattice* const* hs, int count, const int64_t* n, const doub
     img.off_s = align_up(img.off_lut + img.nlut * sizeof(mcl::LutRec), 256);
     img.bytes = img.off_s + 256;
     char* base = (char*)host;
+    // the sweep-offset word and the claim counters start at 0
+    if (base) std::memset(base + img.off_s, 0, 256);
     mcl::GroupDesc* hd = (mcl::GroupDesc*)base;
     uint32_t* htab = base ? (uint32_t*)(base + img.off_bc) : nullptr;
     mcl::LutRec* hlut = base ? (mcl::LutRec*)(base + img.off_lut) : nullptr;
@@ -407,12 +411,13 @@ hipError_t group_launches(const GroupImage& img, const void* dev, int64_t s0, in
     const mcl::GroupDesc* desc = (const mcl::GroupDesc*)b;
     const uint2* tabs = (const uint2*)(b + img.off_bc);
     const mcl::LutRec* luts = (const mcl::LutRec*)(b + img.off_lut);
+    uint32_t* ctr = (uint32_t*)(b + img.off_s) + 16;
     for (int64_t s = s0; s < s0 + k; ++s)
         for (int c = 0; c < 2; ++c)
             for (int j = 0; j < img.nlaunch; ++j) {
                 const GroupLaunch& ln = img.launches[j];
                 const hipError_t e = mcl::launch_group_half(ln.mask, c, desc + ln.first, ln.count, ln.total, ln.grid,
-                                                            tabs, luts, (uint32_t)s, sbase, st);
+                                                            tabs, luts, (uint32_t)s, sbase, ctr, st);
                 if (e != hipSuccess) return e;
             }
     return hipSuccess;
@@ -541,8 +546,6 @@ int group_run(mcl_lattice* const* hs, int count, const int64_t* n, const double*
     }
     rc = group_layout(hs, count, n, beta, D, tun, compute_units(devid), img, sl.host, order.data());
     if (rc) return rc;
-    // the sweep-offset word starts at 0 (graph replays add to it)
-    std::memset((char*)sl.host + img.off_s, 0, 256);
     MCL_HIP(hipMemcpyAsync(sl.dev, sl.host, img.bytes, hipMemcpyHostToDevice, stream));
 
     // graph replays for a shape seen before (and not inside a capture of the caller's)

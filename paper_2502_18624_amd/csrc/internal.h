@@ -114,10 +114,13 @@ constexpr int kMaskIsing = 1, kMaskBC = 2, kMaskLut = 4;
 
 // One colour of sweep s (+ *sbase when sbase is set) for every replica of
 // the list with s < n; grid workgroups (a multiple of 8) walk the `total`
-// tiles, each XCD's workgroups one contiguous eighth of the list.
+// tiles, each XCD's workgroups one contiguous eighth of the list.  With
+// fewer workgroups than tiles they claim tiles from the 16 counter words at
+// ctr, which must be zero before the first such launch and are zero again
+// after each (nullptr: a fixed share per workgroup).
 hipError_t launch_group_half(int mask, int color, const GroupDesc* desc, int count, uint32_t total,
                              uint32_t grid, const uint2* bc_tables, const LutRec* luts, uint32_t s,
-                             const uint32_t* sbase, hipStream_t st);
+                             const uint32_t* sbase, uint32_t* ctr, hipStream_t st);
 // Bucket tables of the 1-bit replicas of a batched call.
 hipError_t launch_group_lut_buckets(const LutRec* luts, int n, hipStream_t st);
 

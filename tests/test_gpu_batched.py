@@ -50,6 +50,26 @@ def _digest(lat):
     return hashlib.sha256(lat.read_packed().tobytes()).hexdigest()
 
 
+def _run_mix_against_plain(mcl, specs, seed):
+    """Three calls of one shape (plain launches, then a captured graph, then
+    its replay under graph tunings), then a new shape with some replicas
+    idle; every replica's packed lattice against its own sweep() run."""
+    rng = np.random.default_rng(seed)
+    calls = [[int(rng.integers(1, 6)) for _ in specs] for _ in range(3)]   # one shape, three calls
+    calls.append([int(rng.integers(0, 3)) for _ in specs])                  # a new shape, some idle
+    lats = [mcl.Lattice(m, L, sd) for (m, L, sd, _, _) in specs]
+    for n in calls:
+        mcl.group_sweep(lats, n, [sp[3] for sp in specs], [sp[4] for sp in specs])
+    for i, (lat, (m, L, sd, b, D)) in enumerate(zip(lats, specs)):
+        ref = mcl.Lattice(m, L, sd)
+        for n in calls:
+            ref.sweep(n[i], b, D)
+        assert lat.t == ref.t == sum(n[i] for n in calls)
+        assert _digest(lat) == _digest(ref), (m, L, sd)
+        ref.free()
+        lat.free()
+
+
 def test_bench_mix_equals_plain_runs(mcl):
     import ctypes
 
@@ -62,20 +82,30 @@ def test_bench_mix_equals_plain_runs(mcl):
         specs = _mix(36, 5)
         tune = autotune_group([(m, L) for (m, L, _, _, _) in specs], sweeps_per_call=4, reps=1)
         print("tuning", {k: v for k, v in tune.items() if k != "rows_log2L"}, flush=True)
-        rng = np.random.default_rng(9)
-        calls = [[int(rng.integers(1, 6)) for _ in specs] for _ in range(3)]   # one shape, three calls
-        calls.append([int(rng.integers(0, 3)) for _ in specs])                  # a new shape, some idle
-        lats = [mcl.Lattice(m, L, sd) for (m, L, sd, _, _) in specs]
-        for n in calls:
-            mcl.group_sweep(lats, n, [sp[3] for sp in specs], [sp[4] for sp in specs])
-        for i, (lat, (m, L, sd, b, D)) in enumerate(zip(lats, specs)):
-            ref = mcl.Lattice(m, L, sd)
-            for n in calls:
-                ref.sweep(n[i], b, D)
-            assert lat.t == ref.t == sum(n[i] for n in calls)
-            assert _digest(lat) == _digest(ref), (m, L, sd)
-            ref.free()
-            lat.free()
+        _run_mix_against_plain(mcl, specs, 9)
+    finally:
+        mcl.lib().mcl_group_tuning_set(ctypes.byref(saved))
+
+
+@pytest.mark.parametrize("wg,split,graph,gsweeps", [(1, 0, 1, 2), (2, 1, 0, 32), (4, 0, 1, 3)])
+def test_bench_mix_persistent_grids(mcl, wg, split, graph, gsweeps):
+    """The same mix on persistent grids of 1, 2 and 4 workgroups per CU:
+    fewer workgroups than tiles, so each eighth of the tile list is claimed
+    tile by tile from its counters, which every launch (graph replays
+    included) must leave at zero for the next.  The 4096 and 8192 replicas
+    take the scalar row walk."""
+    import ctypes
+
+    from paper_2502_18624_amd._lib import GroupTuning
+    print("batched bench mix, persistent", wg, split, graph, gsweeps, flush=True)
+    saved = GroupTuning()
+    mcl.lib().mcl_group_tuning_get(ctypes.byref(saved))
+    try:
+        t = GroupTuning()
+        mcl.lib().mcl_group_tuning_get(ctypes.byref(t))
+        t.use_graph, t.largest_first, t.wg_per_cu, t.split_models, t.graph_sweeps = graph, 1, wg, split, gsweeps
+        assert mcl.lib().mcl_group_tuning_set(ctypes.byref(t)) == 0
+        _run_mix_against_plain(mcl, _mix(36, 6 + wg), 10 + wg)
     finally:
         mcl.lib().mcl_group_tuning_set(ctypes.byref(saved))
 
