@@ -261,6 +261,18 @@ __device__ __forceinline__ void emit_tbits(const uint4& v, uint32_t q, uint32_t 
     }
 }
 
+// v of lane i + 1 (from_right) or lane i - 1 (from_left) of the wave, by a
+// DPP wave shift; the lane at the end without a neighbour gets an
+// unspecified value.
+__device__ __forceinline__ uint32_t from_right(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);    // wave_shl:1
+}
+__device__ __forceinline__ uint32_t from_left(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);    // wave_shr:1
+}
+
 // One pass over both planes: B and M, Q and the value counts, and the
 // Schwinger-Dyson histogram (section 4) of sigma h over every site; with tb
 // set (L >= 512), also the T bits of every row.  A task is a column vector
@@ -281,7 +293,13 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
     uint32_t hist[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) hist[k] = 0;
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < tasks; g += gridDim.x * blockDim.x) {
+    // workgroup ids go round-robin to the 8 XCDs: XCD x takes the x-th
+    // eighth of the workgroups in order, so the tasks beside a workgroup's
+    // (the rest of its bands, the bands above and below) run on the same
+    // XCD at about the same time and the lines they share meet in its L2
+    const uint32_t nb = gridDim.x;
+    const uint32_t blk = (nb & 7u) == 0 ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    for (uint32_t g = blk * blockDim.x + threadIdx.x; g < tasks; g += nb * blockDim.x) {
         const uint32_t q = g % Q;
         const uint32_t y0 = (g / Q) * rows;
         const uint4* a4 = reinterpret_cast<const uint4*>(p0) + q;
@@ -291,6 +309,10 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
         uint4 bup = b4[yu * Q], bmid = b4[(size_t)y0 * Q];
         const uint32_t hwl = (q == 0) ? W - 1 : 4 * q - 1;
         const uint32_t hwr = (4 * q + 4 == W) ? 0 : 4 * q + 4;
+        // the words beside the vector are the neighbouring lanes' end words
+        // (moved across by DPP), except at the ends of the wave or the row
+        const uint32_t lane = threadIdx.x & 63u;
+        const bool edge_l = lane == 0 || q == 0, edge_r = lane == 63 || q + 1 == Q;
         cells += 2 * C::kPerWord * 4 * rows;    // both planes, 4 words a row
         for (uint32_t r = 0; r < rows; ++r) {
             const uint32_t y = y0 + r;
@@ -299,8 +321,10 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
             const bool odd = (y & 1u) != 0;      // colour-0 sites of row y have x = 2 i + (y & 1)
             if (tb) emit_tbits<MODEL>(odd ? bmid : amid, q, y, L, tb);
             // colour 0 looks right (i + 1) on odd rows, colour 1 on even rows
-            const uint32_t bhalo = p1[(size_t)y * W + (odd ? hwr : hwl)];
-            const uint32_t ahalo = p0[(size_t)y * W + (odd ? hwl : hwr)];
+            uint32_t bhalo = odd ? from_right(bmid.x) : from_left(bmid.w);
+            uint32_t ahalo = odd ? from_left(amid.w) : from_right(amid.x);
+            if (odd ? edge_r : edge_l) bhalo = p1[(size_t)y * W + (odd ? hwr : hwl)];
+            if (odd ? edge_l : edge_r) ahalo = p0[(size_t)y * W + (odd ? hwl : hwr)];
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 const uint32_t wb = pick(bmid, d), wa = pick(amid, d);
@@ -932,14 +956,30 @@ uint32_t grid_cap(uint32_t want)
     return want;
 }
 
+// Optional band height of the B/M/Q pass: MCL_MEASURE_ROWS (2 to 64, read
+// at every launch; the largest divisor of L up to it is taken).  Like the
+// grid cap it changes the split of the work only; a test uses it to run the
+// 64-row bands of large lattices at small L.
+int64_t bmq_rows(const Geom& g)
+{
+    if (const char* e = std::getenv("MCL_MEASURE_ROWS")) {
+        const long long v = std::atoll(e);
+        if (v >= 2 && v <= 64) return pick_rows(g.L, v);
+    }
+    return pick_rows(g.L, g.Q * (g.L / 64) >= (int64_t(1) << 20) ? 64 : 32);
+}
+
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s)
 {
-    // one thread per task, bands of 32 rows.  Measured at L = 2^17 (4-bit
-    // Ising): 1.88 ms and 1.39x the lattice's bytes read, against 2.07 ms and
-    // 1.32x for 16-row bands in a persistent grid of 2048 workgroups, and
-    // 2.35 ms and 1.50x for 64-row bands there (longer walks read the halo
-    // lines shared with neighbouring waves more often from HBM)
-    const int64_t rows = pick_rows(g.L, 32);
+    // one thread per task, bands of 64 rows while that leaves 2^20 tasks or
+    // more (else 32).  The words beside a vector come from the neighbouring
+    // lanes, so the lines a pass reads twice are the halo rows of its bands
+    // and those at workgroup edges.  Measured at L = 2^17 (4-bit Ising),
+    // bytes read against the lattice's: 1.50x with every halo word loaded
+    // from memory, 1.12x with lane exchanges, 1.09x with the XCD-aware
+    // workgroup order as well, 1.056x with 64-row bands (16 rows: 1.15x);
+    // 2.06 - 2.09 ms each way once the halo loads were gone.
+    const int64_t rows = bmq_rows(g);
     const int64_t threads = g.Q * (g.L / rows);
     const uint32_t grid = grid_cap((uint32_t)((threads + 255) / 256));
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;

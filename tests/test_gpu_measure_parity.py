@@ -13,7 +13,8 @@ histogram; B, M, Q and the spin counts).
   bits.
 - The same branches at L <= 4096, forced by capping the grid of the
   measurement kernels (MCL_MEASURE_GRID), in protocol and full mode, with
-  several B/M/Q tasks per thread besides.
+  several B/M/Q tasks per thread besides, and with the B/M/Q pass's 64-row
+  bands of L >= 2^16 (MCL_MEASURE_ROWS).
 - t = 10^6: r_c(t) exceeds L/2, so every distance up to L/2 is measured and
   each residue class of the sampled distances spans several chunks.
 - The L = 256 quench of the parity-size workload in full: seed 1001,
@@ -88,13 +89,15 @@ def test_measure_parity_at_32768(mcl, model):
 
 
 @pytest.mark.parametrize("model", [0, 1, 2])
-@pytest.mark.parametrize("mode,L,grid", [(2, 4096, 3), (2, 4096, 1), (1, 512, 3)])
-def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L, grid):
-    """Three workgroups (or one) for the persistent passes, so each takes
-    several tasks, tiles, sampled rows and groups of source-row words, with
-    uneven shares."""
-    print("measure parity split launches", model, mode, L, grid, flush=True)
+@pytest.mark.parametrize("mode,L,grid,rows", [(2, 4096, 3, 0), (2, 4096, 1, 64), (1, 512, 3, 64), (2, 4096, 16, 64)])
+def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L, grid, rows):
+    """Three workgroups (or one, or 16) for the persistent passes, so each
+    takes several tasks, tiles, sampled rows and groups of source-row
+    words, with uneven shares; B/M/Q bands of 64 rows where rows is set."""
+    print("measure parity split launches", model, mode, L, grid, rows, flush=True)
     monkeypatch.setenv("MCL_MEASURE_GRID", str(grid))
+    if rows:
+        monkeypatch.setenv("MCL_MEASURE_ROWS", str(rows))
     beta, D = _params(model)
     lat = mcl.Lattice(model, L, 4500 + model)
     lat.sweep(3, beta, D)
@@ -106,6 +109,7 @@ def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L, grid):
     _compare(m, s, mode, _threads())
     # the knobs change the launch shape only
     monkeypatch.delenv("MCL_MEASURE_GRID")
+    monkeypatch.delenv("MCL_MEASURE_ROWS", raising=False)
     m2 = lat.measure(mode)
     for k in ("B", "M", "Q", "counts", "sd"):
         assert m2[k] == m[k]
