@@ -41,6 +41,16 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int d)
 
 __device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n ? v - n : v; }
 
+// acc + (number of set bits of x) as one v_bcnt_u32_b32.  Written out, sums
+// of several bit counts are re-associated into separate counts and
+// three-input adds.
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // Per-word cell counts: +1 (n = 2), -1 (n = 0), 0 (n = 1); anything else is
 // what they leave.  Bit 0 of each nibble carries the test; the mask of the
 // other bits is folded into `high`, so each count is one three-input
@@ -48,9 +58,9 @@ __device__ __forceinline__ uint32_t wrap(uint32_t v, uint32_t n) { return v >= n
 __device__ __forceinline__ void cell_counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
 {
     const uint32_t b1 = w >> 1, high = (w >> 2) | (w >> 3) | 0xEEEEEEEEu;
-    np1 += popc(b1 & ~w & ~high);
-    nm1 += popc(~(w | b1 | high));
-    n0 += popc(w & ~(b1 | high));
+    np1 = bcnt_acc(b1 & ~w & ~high, np1);
+    nm1 = bcnt_acc(~(w | b1 | high), nm1);
+    n0 = bcnt_acc(w & ~(b1 | high), n0);
 }
 
 // Sum of s * s' over the 8 cell pairs of two words, as (nonzero pairs,
@@ -58,8 +68,8 @@ __device__ __forceinline__ void cell_counts(uint32_t w, uint32_t& np1, uint32_t&
 __device__ __forceinline__ void pair_counts(uint32_t a, uint32_t b, uint32_t& nz, uint32_t& diff)
 {
     const uint32_t z = ~(a | b) & 0x11111111u;
-    nz += popc(z);
-    diff += popc(((a ^ b) >> 1) & z);
+    nz = bcnt_acc(z, nz);
+    diff = bcnt_acc(((a ^ b) >> 1) & z, diff);
 }
 
 // Cell width traits: 4-bit cells (n = s + 1, 8 per word) and 1-bit cells
@@ -97,13 +107,12 @@ struct Cell<1> {
     static __device__ __forceinline__ void pair(uint32_t a, uint32_t b, uint32_t& nz, uint32_t& diff)
     {
         nz += 32;
-        diff += popc(a ^ b);
+        diff = bcnt_acc(a ^ b, diff);
     }
-    static __device__ __forceinline__ void counts(uint32_t w, uint32_t& np1, uint32_t& nm1, uint32_t& n0)
+    // -1 cells: what the +1 cells leave (taken at the end of the pass)
+    static __device__ __forceinline__ void counts(uint32_t w, uint32_t& np1, uint32_t&, uint32_t&)
     {
-        const uint32_t c = popc(w);
-        np1 += c;
-        nm1 += 32 - c;
+        np1 = bcnt_acc(w, np1);
     }
     static __device__ __forceinline__ uint32_t left(uint32_t w, uint32_t prev) { return funnel(w, prev, 31); }
     static __device__ __forceinline__ uint32_t right(uint32_t next, uint32_t w) { return funnel(next, w, 1); }
@@ -178,8 +187,8 @@ __device__ __forceinline__ void sd_add4(uint32_t o, uint32_t a, uint32_t b, uint
     const uint32_t lo[4] = {n0 & n1, b0 & n1, n0 & b1, b0 & b1};
     const uint32_t hi0 = n2 & n3, hi1 = b2 & n3;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) hist[v] += popc(lo[v & 3] & (v < 4 ? hi0 : hi1));
-    hist[8] += popc(b3);
+    for (int v = 0; v < 8; ++v) hist[v] = bcnt_acc(lo[v & 3] & (v < 4 ? hi0 : hi1), hist[v]);
+    hist[8] = bcnt_acc(b3, hist[8]);
 }
 
 // 1-bit cells: t = 2 (aligned neighbours), from the four words of
@@ -192,28 +201,31 @@ __device__ __forceinline__ void sd_add1(uint32_t o, uint32_t a, uint32_t b, uint
     const uint32_t all_ne = d0 & d1 & d2 & d3;                       // 0 aligned: t = 0
     const uint32_t one_ne = (t1 ^ t2) & ~((d0 & d1) | (d2 & d3));    // 3 aligned: t = 6
     const uint32_t one_eq = (t1 ^ t2) & (d0 | d1) & (d2 | d3);       // 1 aligned: t = 2
-    const uint32_t c8 = popc(all_eq), c0 = popc(all_ne), c6 = popc(one_ne), c2 = popc(one_eq);
-    hist[8] += c8;
-    hist[0] += c0;
-    hist[6] += c6;
-    hist[2] += c2;
-    hist[4] += 32u - c8 - c0 - c6 - c2;
+    hist[8] = bcnt_acc(all_eq, hist[8]);
+    hist[0] = bcnt_acc(all_ne, hist[0]);
+    hist[6] = bcnt_acc(one_ne, hist[6]);
+    hist[2] = bcnt_acc(one_eq, hist[2]);
+    // two aligned (t = 4): the rest of the cells, at the end of the pass
 }
 
 // 4-bit Ising cells (n in {0, 2}): per nibble S = 2 d, d the number of
 // neighbours of the opposite sign, 0..4 (each xor nibble is 0 or 2, their
-// sum at most 8).  Adds the histogram of t = sigma h + 4 = 8 - 2 d for
-// d = 1 .. 4; d = 0 takes the rest of the cells, and the bond sum follows
-// from the histogram (both done once, at the end of the pass).
+// sum at most 8), so bits 1, 2, 3 of the nibble are bits 0, 1, 2 of d.
+// With n_k the number of cells with d = k, adds to
+//   e[0] the set bits of S:            n_1 + n_2 + 2 n_3 + n_4,
+//   e[1] those at nibble bit 1:        n_1 + n_3,
+//   e[2] bits 1 and 2 both set:        n_3,
+//   e[3] those at nibble bit 3:        n_4,
+// from which the end of the pass takes n_1 .. n_4; n_0 is the rest of the
+// cells, and the bond sum follows from the histogram.
 __device__ __forceinline__ void sd_add_ising4(uint32_t o, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                              uint32_t (&hist)[9])
+                                              uint32_t (&e)[4])
 {
     const uint32_t S = xad(d, o, xad(c, o, xad(b, o, a ^ o)));
-    const uint32_t p = S >> 1, q = S >> 2, r = S >> 3;   // bits 0, 1, 2 of d at nibble bit 0, 1, 2
-    hist[6] += popc(p & ~q & 0x11111111u);               // d = 1 (d = 4 has bits 0 and 1 clear)
-    hist[4] += popc(q & ~p & 0x11111111u);               // d = 2
-    hist[2] += popc(p & q & 0x11111111u);                // d = 3
-    hist[0] += popc(r & 0x11111111u);                    // d = 4
+    e[0] = bcnt_acc(S, e[0]);
+    e[1] = bcnt_acc(S & 0x22222222u, e[1]);
+    e[2] = bcnt_acc(S & (S << 1) & 0x44444444u, e[2]);
+    e[3] = bcnt_acc(S & 0x88888888u, e[3]);
 }
 
 // T bits (the sampled columns, see below) of row y from the thread's
@@ -279,7 +291,9 @@ __device__ __forceinline__ uint32_t from_left(uint32_t v)
 // q of a band of rows; the thread keeps rows y - 1, y, y + 1 of both
 // planes.  Colour-0 sites carry the bonds (each bond has one colour-0
 // end); both colours add to the counts and the histogram.
-template <int MODEL>
+// WAVE_ROWS: L / (cells per vector) is a multiple of 64, so the 64 lanes of
+// a wave share their band and its row parity is a scalar.
+template <int MODEL, bool WAVE_ROWS>
 __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p0, const uint32_t* __restrict__ p1,
                                                   uint32_t L, uint32_t rows, int64_t* __restrict__ acc,
                                                   uint32_t* __restrict__ tb)
@@ -290,7 +304,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
     const uint32_t Q = L >> C::kVecShift, W = L >> C::kWordShift;
     const uint32_t tasks = Q * (L / rows);
     uint32_t nz = 0, diff = 0, np1 = 0, nm1 = 0, n0 = 0, cells = 0;
-    uint32_t hist[9];
+    uint32_t hist[9], e[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 9; ++k) hist[k] = 0;
     // workgroup ids go round-robin to the 8 XCDs: XCD x takes the x-th
@@ -301,7 +315,8 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
     const uint32_t blk = (nb & 7u) == 0 ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
     for (uint32_t g = blk * blockDim.x + threadIdx.x; g < tasks; g += nb * blockDim.x) {
         const uint32_t q = g % Q;
-        const uint32_t y0 = (g / Q) * rows;
+        uint32_t y0 = (g / Q) * rows;
+        if (WAVE_ROWS) y0 = __builtin_amdgcn_readfirstlane(y0);
         const uint4* a4 = reinterpret_cast<const uint4*>(p0) + q;
         const uint4* b4 = reinterpret_cast<const uint4*>(p1) + q;
         const size_t yu = y0 == 0 ? L - 1 : y0 - 1;
@@ -335,8 +350,8 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
                 C::counts(wa, np1, nm1, n0);
                 C::counts(wb, np1, nm1, n0);
                 if (MODEL == 0) {
-                    sd_add_ising4(wa, pick(bup, d), pick(bdn, d), wb, hb, hist);
-                    sd_add_ising4(wb, pick(aup, d), pick(adn, d), wa, ha, hist);
+                    sd_add_ising4(wa, pick(bup, d), pick(bdn, d), wb, hb, e);
+                    sd_add_ising4(wb, pick(aup, d), pick(adn, d), wa, ha, e);
                     continue;
                 }
                 C::pair(wa, pick(bup, d), nz, diff);
@@ -358,14 +373,24 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
         }
     }
     if (MODEL == 0) {
-        // the thread's cells were 16 per word pair, the rest of the histogram
+        // n_1 .. n_4 from the sums of sd_add_ising4 (t = 8 - 2 d); the
+        // thread's cells were 16 per word pair, the rest of the histogram
         // has d = 0; each bond is seen from both ends, so the bond sum is
         // 2 (cells) - sum of d over all cells
+        hist[2] = e[2];
+        hist[0] = e[3];
+        hist[6] = e[1] - e[2];
+        hist[4] = e[0] - e[1] - e[2] - e[3];
         hist[8] = cells - hist[6] - hist[4] - hist[2] - hist[0];
         nz = 2 * cells;
         diff = 0;
         const uint32_t dsum = hist[6] + 2 * hist[4] + 3 * hist[2] + 4 * hist[0];
         nz -= dsum;
+    }
+    if (MODEL == 2) {
+        // 1-bit cells are all +1 or -1; t = 4 is what the other bins leave
+        nm1 = cells - np1;
+        hist[4] = cells - hist[0] - hist[2] - hist[6] - hist[8];
     }
     // acc: [0] B, [1] M, [2] #(+1), [3] #(-1), [4] #(0), [5 + k] #(sigma h = k - 4);
     // invalid cells are what the three counts leave of L^2 (done on the host)
@@ -388,7 +413,7 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 // an xor (and two ands for Blume-Capel) and the bit counts.
 // ---------------------------------------------------------------------------
 constexpr int kSW = 32;
-constexpr int kTH = 32;
+constexpr int kTH = 64;
 constexpr int kHalo = 32;
 constexpr int kTileRows = kTH + kHalo;
 
@@ -453,14 +478,15 @@ __device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int
     }
 }
 
-// Distances [RLO, RHI] along one axis over the thread's 8 rows of the tile.
+// Distances [RLO, RHI] along one axis over the thread's kTH / 4 rows of the tile.
 template <int MODEL, int AXIS, int RLO, int RHI>
 __device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, int g, int (&acc)[33])
 {
-    // tile rows 8g .. 8g + 7; the tile's first row is even, so the parity of
-    // y + c is that of the local row + c
-    for (int k = 0; k < 8; k += 2) {
-        const int lr = 8 * g + k;
+    // tile rows G g .. G g + G - 1 (G = kTH / 4); the tile's first row is
+    // even, so the parity of y + c is that of the local row + c
+    constexpr int G = kTH / 4;
+    for (int k = 0; k < G; k += 2) {
+        const int lr = G * g + k;
         short_row<MODEL, AXIS, RLO, RHI, 0, 0>(T, lr, j, acc);
         short_row<MODEL, AXIS, RLO, RHI, 1, 1>(T, lr, j, acc);
         short_row<MODEL, AXIS, RLO, RHI, 0, 1>(T, lr + 1, j, acc);
@@ -492,7 +518,8 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
     const uint4* P4 = reinterpret_cast<const uint4*>(planes);
     // thread: word column j; waves 0 and 2 take the x axis, waves 1 and 3 the
     // y axis (uniform per wave); the two 32-lane halves of a wave and the
-    // wave pair give the row group g, rows 8 g .. 8 g + 7 of the tile
+    // wave pair give the row group g, rows G g .. G g + G - 1 of the tile
+    // (G = kTH / 4)
     const int j = threadIdx.x & (kSW - 1);
     const int wave = threadIdx.x >> 6;
     const int axis = wave & 1;
@@ -553,7 +580,7 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
         if (q0 + (uint32_t)j < Wp) {
             if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, acc);
             else short_tile<MODEL, 1>(T, j, g, R, acc);
-            pairs += 512;          // 8 rows x 2 planes x 32 cells, per distance
+            pairs += 16 * kTH;     // kTH / 4 rows x 2 planes x 32 cells, per distance
         }
     }
     int64_t v[66];
@@ -985,12 +1012,23 @@ hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, h
     const uint32_t L = (uint32_t)g.L, R = (uint32_t)rows;
     // the pass writes the T bits from L = 512 on; below, a kernel of its own
     uint32_t* tb = g.L >= 512 ? tbits : nullptr;
-    if (model == 2)
-        hipLaunchKernelGGL(bmq_kernel<2>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
-    else if (model == 1)
-        hipLaunchKernelGGL(bmq_kernel<1>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
-    else
-        hipLaunchKernelGGL(bmq_kernel<0>, dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+    const bool wave_rows = (g.Q & 63) == 0;
+    if (model == 2) {
+        if (wave_rows)
+            hipLaunchKernelGGL((bmq_kernel<2, true>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+        else
+            hipLaunchKernelGGL((bmq_kernel<2, false>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+    } else if (model == 1) {
+        if (wave_rows)
+            hipLaunchKernelGGL((bmq_kernel<1, true>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+        else
+            hipLaunchKernelGGL((bmq_kernel<1, false>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+    } else {
+        if (wave_rows)
+            hipLaunchKernelGGL((bmq_kernel<0, true>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+        else
+            hipLaunchKernelGGL((bmq_kernel<0, false>), dim3(grid), dim3(256), 0, s, g.plane(0), g.plane(1), L, R, acc, tb);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !tbits || tb) return e;
     const uint32_t nw = (uint32_t)(g.L * tbits_words(g.L));
