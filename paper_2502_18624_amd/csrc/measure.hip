@@ -439,6 +439,40 @@ __device__ __forceinline__ uint32_t nibble_bits(const uint4& v, bool invert)
     return r;
 }
 
+// Column index q of a tile word, periodic in the row of Wp words (q < Wp + kSW + 1).
+__device__ __forceinline__ uint32_t wrap_col(uint32_t q, uint32_t Wp)
+{
+    return q < Wp ? q : (Wp > (uint32_t)kSW ? q - Wp : q % Wp);
+}
+
+// Tile rows row, row + step, ... (< kTileRows) of column col (lattice word
+// column qq) of both planes, as 1-bit words; tile row r is lattice row
+// y0 + r, periodic (y0 + r < L + kHalo <= 2 L).
+template <int MODEL>
+__device__ __forceinline__ void tile_load(ShortTile<MODEL>& T, const uint32_t* __restrict__ planes,
+                                          const uint4* __restrict__ P4, size_t plane_units, uint32_t Wp, uint32_t L,
+                                          uint32_t y0, uint32_t row, uint32_t step, uint32_t col, uint32_t qq)
+{
+    constexpr int NB = ShortTile<MODEL>::NB;
+    uint32_t y = y0 + row;
+    if (y >= L) y -= L;
+    for (; row < (uint32_t)kTileRows; row += step) {
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            const size_t at = c * plane_units + (size_t)y * Wp + qq;
+            if (MODEL == 2) {
+                T.v[c][0][row][col] = planes[at];
+            } else {
+                const uint4 v = P4[at];
+                T.v[c][0][row][col] = nibble_bits<1>(v, false);                    // n = 2: s = +1
+                if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+            }
+        }
+        y += step;
+        if (y >= L) y -= L;
+    }
+}
+
 // Distances [RLO, RHI] along one axis (AXIS 0: x, 1: y) for the cells of
 // plane C in tile row lr (PAR: parity of y + C).
 template <int MODEL, int AXIS, int RLO, int RHI, int C, int PAR>
@@ -497,7 +531,8 @@ __device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, in
 template <int MODEL, int AXIS>
 __device__ __forceinline__ void short_tile(const ShortTile<MODEL>& T, int j, int g, int R, int (&acc)[33])
 {
-    short_chunk<MODEL, AXIS, 0, 10>(T, j, g, acc);
+    // r = 0 counts no pair of opposite sign for Ising cells (acc[0] stays 0)
+    short_chunk<MODEL, AXIS, MODEL == 1 ? 0 : 1, 10>(T, j, g, acc);
     if (R > 10) short_chunk<MODEL, AXIS, 11, 21>(T, j, g, acc);
     if (R > 21) short_chunk<MODEL, AXIS, 22, 32>(T, j, g, acc);
 }
@@ -554,28 +589,15 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             __syncthreads();
         }
         const uint32_t row0 = reuse ? (uint32_t)kHalo : 0u;
-        const uint32_t nel = (kTileRows - row0) * (kSW + 1);     // new elements of a plane
-#pragma unroll
-        for (uint32_t c = 0; c < 2; ++c) {
-            for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-                const uint32_t rr = e / (kSW + 1);
-                const uint32_t col = e - rr * (kSW + 1);
-                const uint32_t row = row0 + rr;
-                // y0 + row < L + kTH; q0 + col < Wp + kSW + 1, which wraps once when Wp > kSW
-                uint32_t y = y0 + row;
-                if (y >= L) y -= L;
-                uint32_t qq = q0 + col;
-                if (qq >= Wp) qq = Wp > (uint32_t)kSW ? qq - Wp : qq % Wp;
-                const size_t at = c * plane_units + (size_t)y * Wp + qq;
-                if (MODEL == 2) {
-                    T.v[c][0][row][col] = planes[at];
-                } else {
-                    const uint4 v = P4[at];
-                    T.v[c][0][row][col] = nibble_bits<1>(v, false);            // n = 2: s = +1
-                    if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
-                }
-            }
-        }
+        // the new rows: lane (column lc, row group lg) takes column lc of rows
+        // row0 + lg, row0 + lg + 8, ...; then one thread per row the halo
+        // column kSW.  q0 + col < Wp + kSW + 1, which wraps once when Wp > kSW
+        const uint32_t lc = threadIdx.x & (kSW - 1), lg = threadIdx.x >> 5;
+        tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + lg, blockDim.x / kSW, lc,
+                         wrap_col(q0 + lc, Wp));
+        if (threadIdx.x < kTileRows - row0)
+            tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x, kTileRows, kSW,
+                             wrap_col(q0 + kSW, Wp));
         __syncthreads();
         if (q0 + (uint32_t)j < Wp) {
             if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, acc);
