@@ -423,20 +423,34 @@ struct ShortTile {
     uint32_t v[2][NB][kTileRows][kSW + 1];
 };
 
-// Bit `BIT` of each nibble of the 4 words (32 cells), in cell order.
+// Bit `BIT` (0 or 1) of each nibble of the 4 words (32 cells), in cell
+// order: bit 8 d + k of the result is nibble k of word d.  The words are
+// first interleaved (bit 4 k + d = nibble k of word d: one shift and one bit
+// select each), then the bit index is rotated from (k, d) to (d, k) by three
+// swaps of index bits (0 with 2, 1 with 3, 2 with 4) and a byte permutation
+// (3 with 4).
+template <int S, uint32_t M>
+__device__ __forceinline__ uint32_t delta_swap(uint32_t x)
+{
+    const uint32_t t = ((x >> S) ^ x) & M;
+    return x ^ t ^ (t << S);
+}
+
+__device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
+
 template <int BIT>
 __device__ __forceinline__ uint32_t nibble_bits(const uint4& v, bool invert)
 {
-    uint32_t r = 0;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint32_t x = ((invert ? ~pick(v, d) : pick(v, d)) >> BIT) & 0x11111111u;
-        x = (x | (x >> 3)) & 0x03030303u;
-        x = (x | (x >> 6)) & 0x000F000Fu;
-        x = (x | (x >> 12)) & 0x000000FFu;
-        r |= x << (8 * d);
-    }
-    return r;
+    const uint32_t s0 = BIT ? v.x >> 1 : v.x;
+    const uint32_t s1 = BIT ? v.y : v.y << 1;
+    const uint32_t s2 = v.z << (2 - BIT);
+    const uint32_t s3 = v.w << (3 - BIT);
+    uint32_t z = bit_select(0x11111111u, s0, bit_select(0x22222222u, s1, bit_select(0x88888888u, s3, s2)));
+    if (invert) z = ~z;
+    z = delta_swap<3, 0x0A0A0A0Au>(z);
+    z = delta_swap<6, 0x00CC00CCu>(z);
+    z = delta_swap<12, 0x0000F0F0u>(z);
+    return __builtin_amdgcn_perm(z, z, 0x03010200u);
 }
 
 // Column index q of a tile word, periodic in the row of Wp words (q < Wp + kSW + 1).
@@ -800,37 +814,67 @@ __global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restri
                 R[rr * rowstride + plane * NSW] = v;
             }
         } else if (C::kPerWord == 8) {
-            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
+            // a wave takes 64 consecutive words of the row (2 W of them, both
+            // planes; W is a multiple of 32): the bookkeeping is per wave
+            for (uint32_t idx0 = __builtin_amdgcn_readfirstlane(64u * (uint32_t)wave); idx0 < 2 * W;
+                 idx0 += 64u * (uint32_t)nwaves) {
+                const uint32_t idx = idx0 + (uint32_t)lane;
                 const uint32_t c = idx >= W ? 1u : 0u;
                 const uint32_t w = idx - c * W;
                 const uint32_t word = planes[c * plane_words + (size_t)y * W + w];
                 // lanes 0..31 and 32..63 cover 32 words each, of one plane each
-                const uint32_t idx0 = idx - (uint32_t)lane;
                 const uint32_t c_lo = idx0 >= W ? 1u : 0u, c_hi = idx0 + 32 >= W ? 1u : 0u;
                 const uint32_t k_lo = (idx0 - c_lo * W) >> 5, k_hi = (idx0 + 32 - c_hi * W) >> 5;
+                uint64_t ms[8], mz[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const uint64_t ms = __ballot((word >> (4 * j + 1)) & 1u);
-                    uint64_t mz = 0;
-                    if (NB == 2) mz = __ballot(((~word) >> (4 * j)) & 1u);
+                    ms[j] = __ballot((word >> (4 * j + 1)) & 1u);
+                    mz[j] = NB == 2 ? __ballot(((~word) >> (4 * j)) & 1u) : 0u;
+                }
+                if (c_lo == c_hi) {
+                    // L >= 1024: the two halves are words k_lo, k_lo + 1 (k_lo
+                    // even) of one residue row, 8-byte aligned in LDS
+                    if (lane == 0) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const uint32_t t = 2u * j + c_lo - rho0;       // the residue's slot - 1
+                            if (t < G) {
+                                uint32_t* dst = R + (1 + t) * rowstride + k_lo;
+                                *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)ms[j], (uint32_t)(ms[j] >> 32));
+                                if (NB == 2)
+                                    *reinterpret_cast<uint2*>(dst + NSW) =
+                                        make_uint2((uint32_t)mz[j], (uint32_t)(mz[j] >> 32));
+                            }
+                        }
+                        if (c_lo == 0) {                                   // residue 0: the sources
+                            *reinterpret_cast<uint2*>(R + k_lo) = make_uint2((uint32_t)ms[0], (uint32_t)(ms[0] >> 32));
+                            if (NB == 2)
+                                *reinterpret_cast<uint2*>(R + NSW + k_lo) =
+                                    make_uint2((uint32_t)mz[0], (uint32_t)(mz[0] >> 32));
+                        }
+                    }
+                    continue;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
                     if (lane == 0) {
                         const uint32_t rl_lo = 2 * j + c_lo, rl_hi = 2 * j + c_hi;
                         const int r_lo = sx_row(rl_lo, rho0, G), r_hi = sx_row(rl_hi, rho0, G);
                         if (r_lo >= 0) {
-                            R[r_lo * rowstride + k_lo] = (uint32_t)ms;
-                            if (NB == 2) R[r_lo * rowstride + NSW + k_lo] = (uint32_t)mz;
+                            R[r_lo * rowstride + k_lo] = (uint32_t)ms[j];
+                            if (NB == 2) R[r_lo * rowstride + NSW + k_lo] = (uint32_t)mz[j];
                         }
                         if (r_hi >= 0) {
-                            R[r_hi * rowstride + k_hi] = (uint32_t)(ms >> 32);
-                            if (NB == 2) R[r_hi * rowstride + NSW + k_hi] = (uint32_t)(mz >> 32);
+                            R[r_hi * rowstride + k_hi] = (uint32_t)(ms[j] >> 32);
+                            if (NB == 2) R[r_hi * rowstride + NSW + k_hi] = (uint32_t)(mz[j] >> 32);
                         }
                         if (rl_lo == 0) {                            // the sources
-                            R[k_lo] = (uint32_t)ms;
-                            if (NB == 2) R[NSW + k_lo] = (uint32_t)mz;
+                            R[k_lo] = (uint32_t)ms[j];
+                            if (NB == 2) R[NSW + k_lo] = (uint32_t)mz[j];
                         }
                         if (rl_hi == 0) {
-                            R[k_hi] = (uint32_t)(ms >> 32);
-                            if (NB == 2) R[NSW + k_hi] = (uint32_t)(mz >> 32);
+                            R[k_hi] = (uint32_t)(ms[j] >> 32);
+                            if (NB == 2) R[NSW + k_hi] = (uint32_t)(mz[j] >> 32);
                         }
                     }
                 }
