@@ -1039,11 +1039,17 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         MCL_HIP(mcl::launch_zero(h->Cy, nr, h->stream));
     }
     const int ns = nr - n_all;                          // sampled distances
-    MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, ns > 0 ? h->tbits : nullptr, h->stream));
+    // 4-bit Ising cells with correlations at L >= 4096: the short-distance
+    // tiles give B, M, Q, the histogram and the T bits too, so the lattice is
+    // read once; cells that hold no spin set acc[14], and then the B/M/Q pass
+    // runs after all (below)
+    const bool fused = nr > 0 && mcl::bmq_fused(h->g, h->model);
+    if (!fused) MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, ns > 0 ? h->tbits : nullptr, h->stream));
     if (nr > 0) {
         // every-source distances are r = 0 .. n_all - 1 (position j holds r = j)
         const int rshort = std::min(n_all - 1, 32);
-        MCL_HIP(mcl::launch_corr_short(h->g, h->model, rshort, h->Cx, h->Cy, h->stream));
+        MCL_HIP(mcl::launch_corr_short(h->g, h->model, rshort, h->Cx, h->Cy, fused ? h->acc : nullptr,
+                                       fused && ns > 0 ? h->tbits : nullptr, h->stream));
         if (n_all - 1 > 32)
             MCL_HIP(mcl::launch_corr_all(h->g, h->rdev + 33, n_all - 33, h->Cx + 33, h->Cy + 33, h->stream));
         if (ns > 0) {
@@ -1063,6 +1069,12 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         MCL_HIP(hipMemcpyAsync(out->Cy, h->Cy, nr * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
     }
     MCL_HIP(hipStreamSynchronize(h->stream));
+    if (fused && acc[14] != 0) {
+        MCL_HIP(mcl::launch_zero(h->acc, mcl::kAccSlots, h->stream));
+        MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, nullptr, h->stream));
+        MCL_HIP(hipMemcpyAsync(acc, h->acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+        MCL_HIP(hipStreamSynchronize(h->stream));
+    }
     out->B = acc[0];
     out->M = acc[1];
     out->Q = acc[2] + acc[3];

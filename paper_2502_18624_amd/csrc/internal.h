@@ -61,8 +61,18 @@ inline int64_t tbits_bytes(int model, int64_t L) { return (model == 1 ? 2 : 1) *
 // B, M, Q, counts and the sigma-h histogram into acc; with tbits set, also
 // the T bits of every row (written by the same pass from L = 512 on).
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s);
-// Correlations from every source at r = 0..R (R <= 32), LDS-tiled.
-hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s);
+// Correlations from every source at r = 0..R (R <= 32), LDS-tiled.  With acc
+// set (4-bit Ising cells, L >= 4096, see bmq_fused) the same tiles give what
+// launch_bmq adds to acc, and with tbits set (L a power of two) the T bits;
+// acc[14] then counts the workgroups that met a cell holding no spin, for
+// which the caller must run launch_bmq instead (acc zeroed, tbits null).
+hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, int64_t* acc,
+                             uint32_t* tbits, hipStream_t s);
+// Whether measure() takes B/M/Q from the short-distance tiles when it runs
+// them: 4-bit Ising cells at L >= 4096, unless the environment variable
+// MCL_MEASURE_FUSED is 0 (read at every call).  For 1-bit cells the B/M/Q
+// pass reads a quarter of the bytes and stays the cheaper way.
+bool bmq_fused(const Geom& g, int model);
 // Correlations from every source at distances r[0..nr) (any r <= L/2).
 hipError_t launch_corr_all(const Geom& g, const int32_t* r_dev, int nr, int64_t* Cx, int64_t* Cy,
                            hipStream_t s);

@@ -403,24 +403,32 @@ __global__ __launch_bounds__(256) void bmq_kernel(const uint32_t* __restrict__ p
 
 // ---------------------------------------------------------------------------
 // Correlations, every source, r = 0..R (R <= 32): LDS tile of SW words (+1 halo word
-// on the right for x-partners) by TH source rows (+32 halo rows below for
-// y-partners), both planes, with the cells as 1-bit words of 32 cells: the
-// sign bit for Ising, and for Blume-Capel a second word of nonzero bits.  A
-// 4-bit row vector (32 cells) packs into one word, a 1-bit plane word is
-// stored as it is, so every model has L / 64 words per tile row.  Thread
-// (j, g) handles word column j and rows 4g .. 4g + 3 of the tile, for r in
+// on the right for x-partners, +1 on the left for the B/M/Q work) by TH
+// source rows (+32 halo rows below for y-partners), both planes, with the
+// cells as 1-bit words of 32 cells: the sign bit for Ising, and for
+// Blume-Capel a second word of nonzero bits.  A 4-bit row vector (32 cells)
+// packs into one word, a 1-bit plane word is stored as it is, so every
+// model has L / 64 words per tile row.  Thread (j, g) handles word column j
+// and rows 16 g .. 16 g + 15 of the tile along one axis, for r in
 // [RLO, RHI]: per distance, axis and 32 pairs one funnel shift (x only),
-// an xor (and two ands for Blume-Capel) and the bit counts.
+// an xor (and two ands for Blume-Capel) and the bit counts.  For 4-bit
+// Ising lattices the same tiles also give the B/M/Q sums (tile_bmq), which
+// would otherwise read the 4-bit lattice a second time.
 // ---------------------------------------------------------------------------
 constexpr int kSW = 32;
 constexpr int kTH = 64;
 constexpr int kHalo = 32;
 constexpr int kTileRows = kTH + kHalo;
 
-template <int MODEL>
+// Tile columns: the strip's words 0 .. kSW - 1 at CO .. CO + kSW - 1, the
+// word right of the strip after them, and with LEFT (CO = 1) the word left
+// of it at column 0.
+template <int MODEL, bool LEFT>
 struct ShortTile {
     static constexpr int NB = MODEL == 1 ? 2 : 1;   // bit planes: sign [, nonzero]
-    uint32_t v[2][NB][kTileRows][kSW + 1];
+    static constexpr int CO = LEFT ? 1 : 0;
+    static constexpr int COLS = kSW + 1 + CO;
+    uint32_t v[2][NB][kTileRows][COLS];
 };
 
 // Bit `BIT` (0 or 1) of each nibble of the 4 words (32 cells), in cell
@@ -461,13 +469,15 @@ __device__ __forceinline__ uint32_t wrap_col(uint32_t q, uint32_t Wp)
 
 // Tile rows row, row + step, ... (< kTileRows) of column col (lattice word
 // column qq) of both planes, as 1-bit words; tile row r is lattice row
-// y0 + r, periodic (y0 + r < L + kHalo <= 2 L).
-template <int MODEL>
-__device__ __forceinline__ void tile_load(ShortTile<MODEL>& T, const uint32_t* __restrict__ planes,
+// y0 + r, periodic (y0 + r < L + kHalo <= 2 L).  `bad` collects the bits of
+// 4-bit Ising cells that hold no spin (n other than 0 and 2).
+template <int MODEL, class TT>
+__device__ __forceinline__ void tile_load(TT& T, const uint32_t* __restrict__ planes,
                                           const uint4* __restrict__ P4, size_t plane_units, uint32_t Wp, uint32_t L,
-                                          uint32_t y0, uint32_t row, uint32_t step, uint32_t col, uint32_t qq)
+                                          uint32_t y0, uint32_t row, uint32_t step, uint32_t col, uint32_t qq,
+                                          uint32_t& bad)
 {
-    constexpr int NB = ShortTile<MODEL>::NB;
+    constexpr int NB = TT::NB;
     uint32_t y = y0 + row;
     if (y >= L) y -= L;
     for (; row < (uint32_t)kTileRows; row += step) {
@@ -480,6 +490,7 @@ __device__ __forceinline__ void tile_load(ShortTile<MODEL>& T, const uint32_t* _
                 const uint4 v = P4[at];
                 T.v[c][0][row][col] = nibble_bits<1>(v, false);                    // n = 2: s = +1
                 if (MODEL == 1) T.v[c][NB - 1][row][col] = nibble_bits<0>(v, true);   // n != 1
+                if (MODEL == 0) bad |= (v.x | v.y | v.z | v.w) & 0xDDDDDDDDu;
             }
         }
         y += step;
@@ -489,20 +500,21 @@ __device__ __forceinline__ void tile_load(ShortTile<MODEL>& T, const uint32_t* _
 
 // Distances [RLO, RHI] along one axis (AXIS 0: x, 1: y) for the cells of
 // plane C in tile row lr (PAR: parity of y + C).
-template <int MODEL, int AXIS, int RLO, int RHI, int C, int PAR>
-__device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int j, int (&acc)[33])
+template <int MODEL, int AXIS, int RLO, int RHI, int C, int PAR, class TT>
+__device__ __forceinline__ void short_row(const TT& T, int lr, int j, int (&acc)[33])
 {
-    constexpr int Z = ShortTile<MODEL>::NB - 1;         // plane of nonzero bits (Blume-Capel)
-    const uint32_t o = T.v[C][0][lr][j];
-    const uint32_t oz = MODEL == 1 ? T.v[C][Z][lr][j] : 0u;
+    constexpr int Z = TT::NB - 1;                       // plane of nonzero bits (Blume-Capel)
+    const int jc = j + TT::CO;                          // the strip's word j in the tile
+    const uint32_t o = T.v[C][0][lr][jc];
+    const uint32_t oz = MODEL == 1 ? T.v[C][Z][lr][jc] : 0u;
     uint32_t w0[2], w1[2], z0[2], z1[2];
     if (AXIS == 0) {
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            w0[p] = T.v[p][0][lr][j];
-            w1[p] = T.v[p][0][lr][j + 1];
-            z0[p] = MODEL == 1 ? T.v[p][Z][lr][j] : 0u;
-            z1[p] = MODEL == 1 ? T.v[p][Z][lr][j + 1] : 0u;
+            w0[p] = T.v[p][0][lr][jc];
+            w1[p] = T.v[p][0][lr][jc + 1];
+            z0[p] = MODEL == 1 ? T.v[p][Z][lr][jc] : 0u;
+            z1[p] = MODEL == 1 ? T.v[p][Z][lr][jc + 1] : 0u;
         }
     }
 #pragma unroll
@@ -514,8 +526,8 @@ __device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int
             pv = m ? funnel(w1[pc], w0[pc], m) : w0[pc];
             if (MODEL == 1) pz = m ? funnel(z1[pc], z0[pc], m) : z0[pc];
         } else {
-            pv = T.v[pc][0][lr + r][j];
-            if (MODEL == 1) pz = T.v[pc][Z][lr + r][j];
+            pv = T.v[pc][0][lr + r][jc];
+            if (MODEL == 1) pz = T.v[pc][Z][lr + r][jc];
         }
         if (MODEL != 1) {
             acc[r] += (int)popc(o ^ pv);                // pairs of opposite sign
@@ -527,8 +539,8 @@ __device__ __forceinline__ void short_row(const ShortTile<MODEL>& T, int lr, int
 }
 
 // Distances [RLO, RHI] along one axis over the thread's kTH / 4 rows of the tile.
-template <int MODEL, int AXIS, int RLO, int RHI>
-__device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, int g, int (&acc)[33])
+template <int MODEL, int AXIS, int RLO, int RHI, class TT>
+__device__ __forceinline__ void short_chunk(const TT& T, int j, int g, int (&acc)[33])
 {
     // tile rows G g .. G g + G - 1 (G = kTH / 4); the tile's first row is
     // even, so the parity of y + c is that of the local row + c
@@ -542,8 +554,8 @@ __device__ __forceinline__ void short_chunk(const ShortTile<MODEL>& T, int j, in
     }
 }
 
-template <int MODEL, int AXIS>
-__device__ __forceinline__ void short_tile(const ShortTile<MODEL>& T, int j, int g, int R, int (&acc)[33])
+template <int MODEL, int AXIS, class TT>
+__device__ __forceinline__ void short_tile(const TT& T, int j, int g, int R, int (&acc)[33])
 {
     // r = 0 counts no pair of opposite sign for Ising cells (acc[0] stays 0)
     short_chunk<MODEL, AXIS, MODEL == 1 ? 0 : 1, 10>(T, j, g, acc);
@@ -551,15 +563,73 @@ __device__ __forceinline__ void short_tile(const ShortTile<MODEL>& T, int j, int
     if (R > 21) short_chunk<MODEL, AXIS, 22, 32>(T, j, g, acc);
 }
 
+// The B/M/Q pass on a tile's 1-bit words (4-bit Ising cells): the sites
+// of tile rows 1 .. kTH (lattice rows y0 + 1 .. y0 + kTH, so every row once
+// over the strip's tiles), word column j, both planes; the thread takes rows
+// 1 + f, 9 + f, ... (f = tid / 32, so the two halves of a wave read
+// adjacent rows).  Per word of 32 cells the four neighbour words (other
+// plane: rows r - 1, r + 1, the same index, and index i + 1 or i - 1 by the
+// parity of y + c) give the sigma-h bins as in the B/M/Q pass; the +1 cells
+// are the set sign bits; the T bits of row y are bits 0, 8, 16, 24 of the
+// words of plane y & 1 (the sampled columns x = 0 mod 16), merged over 8
+// lanes into one word.
+template <int MODEL, class TT>
+__device__ __forceinline__ void tile_bmq(const TT& T, uint32_t y0, uint32_t q0, uint32_t L,
+                                         uint32_t Wp, int j, uint32_t* __restrict__ tb, uint32_t (&hist)[9],
+                                         uint32_t& np1, uint32_t& sites)
+{
+    static_assert(TT::CO == 1, "the B/M/Q work needs the word left of the strip");
+    const uint32_t NSW = L >> 9;
+    const int jc = j + 1;
+    const bool in_strip = q0 + (uint32_t)j < Wp;
+    for (uint32_t r = 1 + (threadIdx.x >> 5); r <= (uint32_t)kTH; r += 8) {
+        if (in_strip) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t o = T.v[c][0][r][jc];
+                const uint32_t same = T.v[1 - c][0][r][jc];
+                const uint32_t up = T.v[1 - c][0][r - 1][jc], dn = T.v[1 - c][0][r + 1][jc];
+                // y0 is even, so y + c has the parity of r + c; colour 0
+                // looks right (i + 1) on odd rows, colour 1 on even rows
+                const uint32_t side = ((r + c) & 1u) ? funnel(T.v[1 - c][0][r][jc + 1], same, 1)
+                                                     : funnel(same, T.v[1 - c][0][r][jc - 1], 31);
+                sd_add1(o, up, dn, same, side, hist);
+                np1 = bcnt_acc(o, np1);
+            }
+            sites += 64;
+        }
+        if (tb) {
+            // protocol lattices (L a power of two >= 4096): every lane of the
+            // strip is in it.  Lane 8 m + 7 of a DPP row gathers lanes
+            // 8 m .. 8 m + 7 by three shifts within the row.
+            const uint32_t x = T.v[r & 1u][0][r][jc] & 0x01010101u;
+            uint32_t w = ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu) << (4 * (j & 7));
+            w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x111, 0xF, 0xF, true);   // row_shr:1
+            w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x112, 0xF, 0xF, true);   // row_shr:2
+            w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x114, 0xF, 0xF, true);   // row_shr:4
+            uint32_t y = y0 + r;
+            if (y >= L) y -= L;
+            if ((j & 7) == 7) tb[(size_t)y * NSW + ((q0 + (uint32_t)j) >> 3)] = w;
+        }
+    }
+}
+
 // Persistent over tiles: each workgroup loads tiles (strip of kSW words by
 // kTH rows, both planes, with halos) in turn and keeps its per-distance sums
-// in registers; one atomic per value per workgroup at the end.
-template <int MODEL>
+// in registers; one atomic per value per workgroup at the end.  FUSED (4-bit
+// Ising cells, L >= 4096): the tiles also give B, M, the counts, the sigma-h
+// histogram and the T bits (tile_bmq), so the B/M/Q pass need not read the
+// lattice again; acc[14] counts the workgroups that saw a cell holding no
+// spin, for which the caller runs the B/M/Q pass after all.
+template <int MODEL, bool FUSED>
 __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restrict__ planes, uint32_t L, int R,
-                                                         int64_t* __restrict__ Cx, int64_t* __restrict__ Cy)
+                                                         int64_t* __restrict__ Cx, int64_t* __restrict__ Cy,
+                                                         int64_t* __restrict__ acc, uint32_t* __restrict__ tb)
 {
-    __shared__ ShortTile<MODEL> T;
+    using TT = ShortTile<MODEL, FUSED>;
+    __shared__ TT T;
     __shared__ int64_t red[4][66];
+    __shared__ int64_t red_bmq[4][15];
     const uint32_t Wp = L >> 6;                     // tile words per row, every model
     const uint32_t nstrips = (Wp + kSW - 1) / kSW;
     const uint32_t ntiles = nstrips * (L / kTH);
@@ -573,17 +643,22 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
     const int wave = threadIdx.x >> 6;
     const int axis = wave & 1;
     const int g = ((wave >> 1) << 1) | ((threadIdx.x >> 5) & 1);
-    int acc[33];
+    int cacc[33];
 #pragma unroll
-    for (int k = 0; k < 33; ++k) acc[k] = 0;
+    for (int k = 0; k < 33; ++k) cacc[k] = 0;
     int64_t pairs = 0;
+    uint32_t bad = 0, np1 = 0, sites = 0;
+    uint32_t hist[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) hist[k] = 0;
     // each workgroup takes a contiguous run of tiles, strip by strip and top
     // to bottom within a strip, so a tile's 32 halo rows are the next tile's
     // source rows: they move up in LDS and only 32 new rows are loaded
     const uint32_t RT = L / kTH;                    // row tiles per strip
     const uint32_t t_begin = (uint32_t)((uint64_t)blockIdx.x * ntiles / gridDim.x);
     const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
-    constexpr uint32_t NB = ShortTile<MODEL>::NB;
+    constexpr uint32_t NB = TT::NB;
+    constexpr uint32_t COLS = TT::COLS, CO = TT::CO;
     for (uint32_t tile = t_begin; tile < t_end; ++tile) {
         const uint32_t strip = tile / RT;
         const uint32_t rt = tile - strip * RT;
@@ -593,40 +668,56 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
         __syncthreads();
         if (reuse) {
             // rows kTH .. kTH + kHalo - 1 become rows 0 .. kHalo - 1, one
-            // (plane, bit plane) block of kTileRows x (kSW + 1) words at a time
+            // (plane, bit plane) block of kTileRows x COLS words at a time
 #pragma unroll
             for (uint32_t blk = 0; blk < 2 * NB; ++blk) {
                 uint32_t* base = &T.v[blk / NB][blk % NB][0][0];
-                for (uint32_t o = threadIdx.x; o < kHalo * (kSW + 1); o += blockDim.x)
-                    base[o] = base[o + kTH * (kSW + 1)];
+                for (uint32_t o = threadIdx.x; o < kHalo * COLS; o += blockDim.x)
+                    base[o] = base[o + kTH * COLS];
             }
             __syncthreads();
         }
         const uint32_t row0 = reuse ? (uint32_t)kHalo : 0u;
         // the new rows: lane (column lc, row group lg) takes column lc of rows
-        // row0 + lg, row0 + lg + 8, ...; then one thread per row the halo
-        // column kSW.  q0 + col < Wp + kSW + 1, which wraps once when Wp > kSW
+        // row0 + lg, row0 + lg + 8, ...; then one thread per row each halo
+        // column (the words left and right of the strip, periodic in the row)
         const uint32_t lc = threadIdx.x & (kSW - 1), lg = threadIdx.x >> 5;
-        tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + lg, blockDim.x / kSW, lc,
-                         wrap_col(q0 + lc, Wp));
+        tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + lg, blockDim.x / kSW, lc + CO,
+                         wrap_col(q0 + lc, Wp), bad);
         if (threadIdx.x < kTileRows - row0)
-            tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x, kTileRows, kSW,
-                             wrap_col(q0 + kSW, Wp));
+            tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x, kTileRows, kSW + CO,
+                             wrap_col(q0 + kSW, Wp), bad);
+        else if (FUSED && threadIdx.x >= 128 && threadIdx.x - 128 < kTileRows - row0)
+            tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x - 128, kTileRows, 0,
+                             (q0 + Wp - 1) % Wp, bad);
         __syncthreads();
         if (q0 + (uint32_t)j < Wp) {
-            if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, acc);
-            else short_tile<MODEL, 1>(T, j, g, R, acc);
+            if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, cacc);
+            else short_tile<MODEL, 1>(T, j, g, R, cacc);
             pairs += 16 * kTH;     // kTH / 4 rows x 2 planes x 32 cells, per distance
         }
+        if constexpr (FUSED) tile_bmq<MODEL>(T, y0, q0, L, Wp, j, tb, hist, np1, sites);
     }
     int64_t v[66];
 #pragma unroll
     for (int k = 0; k < 33; ++k) {
-        const int64_t sk = k > R ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)acc[k] : (int64_t)acc[k]);
+        const int64_t sk = k > R ? 0 : (MODEL != 1 ? pairs - 2 * (int64_t)cacc[k] : (int64_t)cacc[k]);
         v[k] = axis == 0 ? sk : 0;
         v[33 + k] = axis == 1 ? sk : 0;
     }
     block_add_xy<33>(v, Cx, Cy, red);
+    if (FUSED) {
+        // t = 4 (two aligned neighbours) is the rest; each bond is seen from
+        // both ends, so B = 2 N - sum of d over the sites (d = (8 - t) / 2)
+        hist[4] = sites - hist[0] - hist[2] - hist[6] - hist[8];
+        const int64_t dsum = (int64_t)hist[6] + 2 * (int64_t)hist[4] + 3 * (int64_t)hist[2] + 4 * (int64_t)hist[0];
+        int64_t w[15] = {2 * (int64_t)sites - dsum, 2 * (int64_t)np1 - (int64_t)sites, (int64_t)np1,
+                         (int64_t)sites - (int64_t)np1, 0};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) w[5 + k] = (int64_t)hist[k];
+        w[14] = __syncthreads_or(bad != 0) && threadIdx.x == 0 ? 1 : 0;
+        block_add<15>(w, acc, red_bmq);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1108,7 +1199,15 @@ hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, h
     return hipGetLastError();
 }
 
-hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, hipStream_t s)
+bool bmq_fused(const Geom& g, int model)
+{
+    if (model != 0 || g.L < 4096) return false;
+    if (const char* e = std::getenv("MCL_MEASURE_FUSED")) return std::atoi(e) != 0;
+    return true;
+}
+
+hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, int64_t* acc,
+                             uint32_t* tbits, hipStream_t s)
 {
     if (R < 0) return hipSuccess;
     const uint32_t Wp = (uint32_t)(g.L >> 6);
@@ -1116,12 +1215,16 @@ hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64
     const uint32_t ntiles = nstrips * (uint32_t)(g.L / kTH);
     const dim3 grid(grid_cap(std::min<uint32_t>(ntiles, 1024)));
     const uint32_t L = (uint32_t)g.L;
-    if (model == 0)
-        hipLaunchKernelGGL((corr_short_kernel<0>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
-    else if (model == 1)
-        hipLaunchKernelGGL((corr_short_kernel<1>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
-    else
-        hipLaunchKernelGGL((corr_short_kernel<2>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy);
+    if (acc && (model != 0 || g.L < 4096 || (tbits && (Wp % kSW) != 0))) return hipErrorInvalidValue;
+    if (acc) {
+        hipLaunchKernelGGL((corr_short_kernel<0, true>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy, acc, tbits);
+    } else if (model == 0) {
+        hipLaunchKernelGGL((corr_short_kernel<0, false>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy, acc, tbits);
+    } else if (model == 1) {
+        hipLaunchKernelGGL((corr_short_kernel<1, false>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy, acc, tbits);
+    } else {
+        hipLaunchKernelGGL((corr_short_kernel<2, false>), grid, dim3(256), 0, s, g.plane0, L, R, Cx, Cy, acc, tbits);
+    }
     return hipGetLastError();
 }
 

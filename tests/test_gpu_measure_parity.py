@@ -9,12 +9,16 @@ histogram; B, M, Q and the spin counts).
   runs the branches the 2^17 benchmark runs: workgroups with several tiles
   of the short-distance pass (reusing halo rows), several rows of the
   sampled x pass with several words per lane, several distance chunks of
-  the sampled y pass, and the B/M/Q pass writing the sampled columns'
-  bits.
+  the sampled y pass, and the pass that writes the sampled columns' bits
+  (for 4-bit Ising cells the short-distance tiles, which give B, M, Q and
+  the histogram too; otherwise the B/M/Q pass).  Without correlations
+  the B/M/Q pass runs for every model, and gives the same sums.
 - The same branches at L <= 4096, forced by capping the grid of the
   measurement kernels (MCL_MEASURE_GRID), in protocol and full mode, with
   several B/M/Q tasks per thread besides, and with the B/M/Q pass's 64-row
-  bands of L >= 2^16 (MCL_MEASURE_ROWS).
+  bands of L >= 2^16 (MCL_MEASURE_ROWS); at L = 4096 the 4-bit Ising sums
+  both from the short-distance tiles and from the B/M/Q pass
+  (MCL_MEASURE_FUSED).
 - t = 10^6: r_c(t) exceeds L/2, so every distance up to L/2 is measured and
   each residue class of the sampled distances spans several chunks.
 - The L = 256 quench of the parity-size workload in full: seed 1001,
@@ -79,8 +83,11 @@ def test_measure_parity_at_32768(mcl, model):
     lat = mcl.Lattice(model, L, seed)
     lat.sweep(n, beta, D)
     m = lat.measure(mcl.CORR_PROTOCOL)
+    m0 = lat.measure(mcl.CORR_NONE)
     s = lat.read()
     lat.free()
+    for k in ("B", "M", "Q", "counts", "invalid", "sd"):
+        assert m0[k] == m[k], k
     want = oracle.init(model, L, seed)
     oracle.sweep(want, model, seed, 0, n, beta, D, nthreads=nt)
     assert np.array_equal(s, want), "lattice differs at %d sites" % int((s != want).sum())
@@ -107,14 +114,19 @@ def test_measure_parity_split_launches(mcl, monkeypatch, model, mode, L, grid, r
     oracle.sweep(want, model, 4500 + model, 0, 3, beta, D, nthreads=_threads())
     assert np.array_equal(s, want)
     _compare(m, s, mode, _threads())
-    # the knobs change the launch shape only
+    # the knobs change the launch shape only; at L = 4096 the 4-bit Ising
+    # sums come from the short-distance tiles, or (MCL_MEASURE_FUSED=0) from
+    # the B/M/Q pass
     monkeypatch.delenv("MCL_MEASURE_GRID")
     monkeypatch.delenv("MCL_MEASURE_ROWS", raising=False)
-    m2 = lat.measure(mode)
-    for k in ("B", "M", "Q", "counts", "sd"):
-        assert m2[k] == m[k]
-    for k in ("r", "Cx", "Cy", "nsrc"):
-        assert np.array_equal(m2[k], m[k])
+    for fused in ("1", "0"):
+        monkeypatch.setenv("MCL_MEASURE_FUSED", fused)
+        m2 = lat.measure(mode)
+        for k in ("B", "M", "Q", "counts", "sd"):
+            assert m2[k] == m[k]
+        for k in ("r", "Cx", "Cy", "nsrc"):
+            assert np.array_equal(m2[k], m[k])
+    monkeypatch.delenv("MCL_MEASURE_FUSED")
 
 
 @pytest.mark.parametrize("model", [0, 1, 2])

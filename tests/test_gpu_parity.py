@@ -347,12 +347,15 @@ def test_band_heights(mcl, model, L, rows):
 
 
 @pytest.mark.parametrize("model", [0, 1])
-def test_counts_report_cells_that_hold_no_spin(mcl, model):
+@pytest.mark.parametrize("L", [512, 4096])
+def test_counts_report_cells_that_hold_no_spin(mcl, model, L):
     """A packed lattice with some nibbles set to values no spin has (3 .. 15,
     and 1, the Blume-Capel zero, in an Ising lattice): the +1 / 0 / -1
-    counts and the invalid count equal those of the cells as written."""
-    print("invalid cells", model, flush=True)
-    L = 512
+    counts and the invalid count equal those of the cells as written.  At
+    L = 4096 with correlations, where the short-distance tiles of 4-bit
+    Ising cells take over the B/M/Q pass, such cells send the pass back to
+    its own kernel: every sum but the correlations is the one without them."""
+    print("invalid cells", model, L, flush=True)
     lat = mcl.Lattice(model, L, 77 + model)
     buf = lat.read_packed().copy()
     rng = np.random.default_rng(5 + model)
@@ -367,3 +370,7 @@ def test_counts_report_cells_that_hold_no_spin(mcl, model):
     assert m["counts"] == want
     assert m["invalid"] == int((nib > 2).sum()) > 0
     assert sum(m["counts"]) + m["invalid"] == L * L
+    if L >= 4096:
+        mc = lat.measure(mcl.CORR_PROTOCOL)
+        for k in ("B", "M", "Q", "counts", "invalid", "sd"):
+            assert mc[k] == m[k], k
