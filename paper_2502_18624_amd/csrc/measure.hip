@@ -850,8 +850,12 @@ __global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__
 // r = 16 m + rho are R_rho shifted by m: per word of 32 sources one funnel
 // shift, one xor and the bit counts.  LDS holds R_0 and the residues rho0 ..
 // rho0 + G - 1 (the host runs 16 / G passes when a row of all 16 residues
-// does not fit).  Wave w owns the distances k = w, w + 16, ... and sums
-// them over all words of the row.
+// does not fit), each residue row twice in a row, so the partner words
+// w + m / 32 and the next need no wrap.  Wave w of n owns the distances
+// k = w, w + n, ...: per row each lane sums its words, four DPP adds sum 16
+// lanes and the lanes 15, 31, 47, 63 add those to the distance's LDS sum.
+// Workgroups of 512 threads, several per CU, so one loads its next row
+// while another works on its own.
 //
 // Building the residue rows (L >= 512): a 4-bit word w of plane c holds the
 // cells x = 16 w + 2 j + c, j = 0 .. 7, i.e. bit w of residues 2 j + c, so a
@@ -859,13 +863,15 @@ __global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__
 // A 1-bit word w of plane c holds x = 64 w + 2 k + c: bit k belongs to
 // residue 2 (k & 7) + c at position 4 w + (k >> 3), four bits per residue,
 // gathered per lane and merged over 8 lanes.
+constexpr uint32_t kSxU = 4;        // row loads in flight per thread
+
 __device__ __forceinline__ int sx_row(uint32_t rho, uint32_t rho0, uint32_t G)
 {
     return rho - rho0 < G ? (int)(1 + rho - rho0) : -1;
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+__global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restrict__ planes, uint32_t L,
                                                        const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
                                                        uint32_t G, int64_t* __restrict__ Cx)
 {
@@ -874,11 +880,14 @@ __global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restri
     extern __shared__ int sxb_lds[];
     int* sums = sxb_lds;
     int* rl = sxb_lds + nr;
-    uint32_t* R = reinterpret_cast<uint32_t*>(sxb_lds + 2 * nr);    // [(1 + G) rows][NB][NSW]
+    uint32_t* R = reinterpret_cast<uint32_t*>(sxb_lds + 2 * nr);    // [(1 + G) rows][NB][2 NSW]
     const uint32_t W = L >> C::kWordShift, NS = L >> 4;
     const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
-    const uint32_t rowstride = NB * NSW;
+    const uint32_t PO = 2 * NSW;                          // bit plane offset within a row
+    const uint32_t rowstride = NB * PO;
     const bool full = L >= 512;
+    // Ising rows without invalid bits: a word's sum is 32 - 2 (differing bits)
+    const bool diff_only = MODEL != 1 && full;
     const uint32_t valid = full ? 0xFFFFFFFFu : (NS >= 32 ? 0xFFFFFFFFu : ((1u << NS) - 1u));
     const size_t plane_words = (size_t)L * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -887,8 +896,10 @@ __global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restri
         sums[k] = 0;
         rl[k] = rlist[k];
     }
+    uint32_t rows_done = 0;
     for (uint32_t b = blockIdx.x; b < NS; b += gridDim.x) {
         const uint32_t y = 16 * b;
+        ++rows_done;
         __syncthreads();
         if (L < 512) {
             // one word per residue row, its NS bits repeated
@@ -902,122 +913,169 @@ __global__ __launch_bounds__(1024) void corr_sxb_kernel(const uint32_t* __restri
                     const int s = C::spin(row, (16u * (j % NS) + rho) >> 1);
                     v |= ((plane == 0 ? s > 0 : s != 0) ? 1u : 0u) << j;
                 }
-                R[rr * rowstride + plane * NSW] = v;
+                R[rr * rowstride + plane * PO] = v;
             }
         } else if (C::kPerWord == 8) {
-            // a wave takes 64 consecutive words of the row (2 W of them, both
-            // planes; W is a multiple of 32): the bookkeeping is per wave
-            for (uint32_t idx0 = __builtin_amdgcn_readfirstlane(64u * (uint32_t)wave); idx0 < 2 * W;
-                 idx0 += 64u * (uint32_t)nwaves) {
-                const uint32_t idx = idx0 + (uint32_t)lane;
-                const uint32_t c = idx >= W ? 1u : 0u;
-                const uint32_t w = idx - c * W;
-                const uint32_t word = planes[c * plane_words + (size_t)y * W + w];
-                // lanes 0..31 and 32..63 cover 32 words each, of one plane each
-                const uint32_t c_lo = idx0 >= W ? 1u : 0u, c_hi = idx0 + 32 >= W ? 1u : 0u;
-                const uint32_t k_lo = (idx0 - c_lo * W) >> 5, k_hi = (idx0 + 32 - c_hi * W) >> 5;
-                uint64_t ms[8], mz[8];
+            // a wave takes 64 consecutive words of the row at a time (2 W of
+            // them, both planes; W is a multiple of 32, so a group of 64 is
+            // whole): the bookkeeping is per wave.  The loads of kSxU groups
+            // are issued together, so a wave waits for memory once per kSxU
+            // groups rather than once per group.
+            const uint32_t step = 64u * (uint32_t)nwaves;
+            for (uint32_t base = __builtin_amdgcn_readfirstlane(64u * (uint32_t)wave); base < 2 * W;
+                 base += kSxU * step) {
+                uint32_t words[kSxU];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    ms[j] = __ballot((word >> (4 * j + 1)) & 1u);
-                    mz[j] = NB == 2 ? __ballot(((~word) >> (4 * j)) & 1u) : 0u;
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t idx = base + u * step + (uint32_t)lane;
+                    const uint32_t c = idx >= W ? 1u : 0u;
+                    words[u] = idx < 2 * W ? planes[c * plane_words + (size_t)y * W + (idx - c * W)] : 0u;
                 }
-                if (c_lo == c_hi) {
-                    // L >= 1024: the two halves are words k_lo, k_lo + 1 (k_lo
-                    // even) of one residue row, 8-byte aligned in LDS
-                    if (lane == 0) {
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const uint32_t t = 2u * j + c_lo - rho0;       // the residue's slot - 1
-                            if (t < G) {
-                                uint32_t* dst = R + (1 + t) * rowstride + k_lo;
-                                *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)ms[j], (uint32_t)(ms[j] >> 32));
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t idx0 = base + u * step;
+                    if (idx0 >= 2 * W) break;
+                    const uint32_t word = words[u];
+                    // lanes 0..31 and 32..63 cover 32 words each, of one plane each
+                    const uint32_t c_lo = idx0 >= W ? 1u : 0u, c_hi = idx0 + 32 >= W ? 1u : 0u;
+                    const uint32_t k_lo = (idx0 - c_lo * W) >> 5, k_hi = (idx0 + 32 - c_hi * W) >> 5;
+                    uint64_t ms[8], mz[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        ms[j] = __ballot((word >> (4 * j + 1)) & 1u);
+                        mz[j] = NB == 2 ? __ballot(((~word) >> (4 * j)) & 1u) : 0u;
+                    }
+                    if (c_lo == c_hi) {
+                        // L >= 1024: the two halves are words k_lo, k_lo + 1 (k_lo
+                        // even) of one residue row, 8-byte aligned in LDS
+                        if (lane == 0) {
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) {
+                                const uint32_t t = 2u * j + c_lo - rho0;       // the residue's slot - 1
+                                if (t < G) {
+                                    uint32_t* dst = R + (1 + t) * rowstride + k_lo;
+                                    *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)ms[j], (uint32_t)(ms[j] >> 32));
+                                    if (NB == 2)
+                                        *reinterpret_cast<uint2*>(dst + PO) =
+                                            make_uint2((uint32_t)mz[j], (uint32_t)(mz[j] >> 32));
+                                }
+                            }
+                            if (c_lo == 0) {                                   // residue 0: the sources
+                                *reinterpret_cast<uint2*>(R + k_lo) = make_uint2((uint32_t)ms[0], (uint32_t)(ms[0] >> 32));
                                 if (NB == 2)
-                                    *reinterpret_cast<uint2*>(dst + NSW) =
-                                        make_uint2((uint32_t)mz[j], (uint32_t)(mz[j] >> 32));
+                                    *reinterpret_cast<uint2*>(R + PO + k_lo) =
+                                        make_uint2((uint32_t)mz[0], (uint32_t)(mz[0] >> 32));
                             }
                         }
-                        if (c_lo == 0) {                                   // residue 0: the sources
-                            *reinterpret_cast<uint2*>(R + k_lo) = make_uint2((uint32_t)ms[0], (uint32_t)(ms[0] >> 32));
-                            if (NB == 2)
-                                *reinterpret_cast<uint2*>(R + NSW + k_lo) =
-                                    make_uint2((uint32_t)mz[0], (uint32_t)(mz[0] >> 32));
-                        }
+                        continue;
                     }
-                    continue;
-                }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (lane == 0) {
-                        const uint32_t rl_lo = 2 * j + c_lo, rl_hi = 2 * j + c_hi;
-                        const int r_lo = sx_row(rl_lo, rho0, G), r_hi = sx_row(rl_hi, rho0, G);
-                        if (r_lo >= 0) {
-                            R[r_lo * rowstride + k_lo] = (uint32_t)ms[j];
-                            if (NB == 2) R[r_lo * rowstride + NSW + k_lo] = (uint32_t)mz[j];
-                        }
-                        if (r_hi >= 0) {
-                            R[r_hi * rowstride + k_hi] = (uint32_t)(ms[j] >> 32);
-                            if (NB == 2) R[r_hi * rowstride + NSW + k_hi] = (uint32_t)(mz[j] >> 32);
-                        }
-                        if (rl_lo == 0) {                            // the sources
-                            R[k_lo] = (uint32_t)ms[j];
-                            if (NB == 2) R[NSW + k_lo] = (uint32_t)mz[j];
-                        }
-                        if (rl_hi == 0) {
-                            R[k_hi] = (uint32_t)(ms[j] >> 32);
-                            if (NB == 2) R[NSW + k_hi] = (uint32_t)(mz[j] >> 32);
+                    for (int j = 0; j < 8; ++j) {
+                        if (lane == 0) {
+                            const uint32_t rl_lo = 2 * j + c_lo, rl_hi = 2 * j + c_hi;
+                            const int r_lo = sx_row(rl_lo, rho0, G), r_hi = sx_row(rl_hi, rho0, G);
+                            if (r_lo >= 0) {
+                                R[r_lo * rowstride + k_lo] = (uint32_t)ms[j];
+                                if (NB == 2) R[r_lo * rowstride + PO + k_lo] = (uint32_t)mz[j];
+                            }
+                            if (r_hi >= 0) {
+                                R[r_hi * rowstride + k_hi] = (uint32_t)(ms[j] >> 32);
+                                if (NB == 2) R[r_hi * rowstride + PO + k_hi] = (uint32_t)(mz[j] >> 32);
+                            }
+                            if (rl_lo == 0) {                            // the sources
+                                R[k_lo] = (uint32_t)ms[j];
+                                if (NB == 2) R[PO + k_lo] = (uint32_t)mz[j];
+                            }
+                            if (rl_hi == 0) {
+                                R[k_hi] = (uint32_t)(ms[j] >> 32);
+                                if (NB == 2) R[PO + k_hi] = (uint32_t)(mz[j] >> 32);
+                            }
                         }
                     }
                 }
             }
         } else {
-            for (uint32_t idx = threadIdx.x; idx < 2 * W; idx += blockDim.x) {
-                const uint32_t c = idx >= W ? 1u : 0u;
-                const uint32_t w = idx - c * W;
-                const uint32_t word = planes[c * plane_words + (size_t)y * W + w];
+            // as above, the loads of kSxU words per thread issued together
+            for (uint32_t base = threadIdx.x; base < 2 * W; base += kSxU * blockDim.x) {
+                uint32_t words[kSxU];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const uint32_t x = (word >> j) & 0x01010101u;     // bits j, j + 8, j + 16, j + 24
-                    const uint32_t nib = (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu;
-                    uint32_t v = nib << (4u * (w & 7u));
-                    v |= __shfl_xor(v, 1);
-                    v |= __shfl_xor(v, 2);
-                    v |= __shfl_xor(v, 4);
-                    if ((w & 7u) == 0) {
-                        const uint32_t rho = 2 * j + c;
-                        const int rr = sx_row(rho, rho0, G);
-                        if (rr >= 0) R[rr * rowstride + (w >> 3)] = v;
-                        if (rho == 0) R[w >> 3] = v;
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t idx = base + u * blockDim.x;
+                    const uint32_t c = idx >= W ? 1u : 0u;
+                    words[u] = idx < 2 * W ? planes[c * plane_words + (size_t)y * W + (idx - c * W)] : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t idx = base + u * blockDim.x;
+                    if (idx >= 2 * W) break;
+                    const uint32_t c = idx >= W ? 1u : 0u;
+                    const uint32_t w = idx - c * W;
+                    const uint32_t word = words[u];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint32_t x = (word >> j) & 0x01010101u;     // bits j, j + 8, j + 16, j + 24
+                        const uint32_t nib = (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu;
+                        uint32_t v = nib << (4u * (w & 7u));
+                        v |= __shfl_xor(v, 1);
+                        v |= __shfl_xor(v, 2);
+                        v |= __shfl_xor(v, 4);
+                        if ((w & 7u) == 0) {
+                            const uint32_t rho = 2 * j + c;
+                            const int rr = sx_row(rho, rho0, G);
+                            if (rr >= 0) R[rr * rowstride + (w >> 3)] = v;
+                            if (rho == 0) R[w >> 3] = v;
+                        }
                     }
                 }
             }
         }
         __syncthreads();
+        // the second copy of each residue row
+        for (uint32_t t = threadIdx.x; t < G * NB * NSW; t += blockDim.x) {
+            const uint32_t rr = 1 + t / (NB * NSW), rest = t % (NB * NSW);
+            const uint32_t pl = rest / NSW, w = rest - pl * NSW;
+            uint32_t* row = R + rr * rowstride + pl * PO;
+            row[NSW + w] = row[w];
+        }
+        __syncthreads();
         for (int k = wave; k < nr; k += nwaves) {
-            const uint32_t r = (uint32_t)rl[k];
+            const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane(rl[k]);
             const int rr = sx_row(r & 15u, rho0, G);
             if (rr < 0) continue;                                 // another pass's residue
             const uint32_t m = r >> 4;
-            const uint32_t ws = m >> 5, sh = m & 31u;
-            const uint32_t* P = R + rr * rowstride;
-            int acc = 0;
-            for (uint32_t w = lane; w < NSW; w += 64) {
-                const uint32_t w0 = (w + ws) & (NSW - 1), w1 = (w0 + 1) & (NSW - 1);
-                const uint32_t p = funnel(P[w1], P[w0], sh);
-                uint32_t sz = 0, pz = 0;
-                if (NB == 2) {
-                    sz = R[NSW + w];
-                    pz = funnel(P[NSW + w1], P[NSW + w0], sh);
+            const uint32_t* P = R + rr * rowstride + (m >> 5);
+            const uint32_t sh = m & 31u;
+            int a = 0;
+            for (uint32_t w0 = 0; w0 < NSW; w0 += 64) {
+                const uint32_t w = w0 + (uint32_t)lane;
+                if (w < NSW) {
+                    const uint32_t p = funnel(P[w + 1], P[w], sh);
+                    if (diff_only) {
+                        a = (int)bcnt_acc(R[w] ^ p, (uint32_t)a);
+                    } else {
+                        uint32_t sz = 0, pz = 0;
+                        if (NB == 2) {
+                            sz = R[PO + w];
+                            pz = funnel(P[PO + w + 1], P[PO + w], sh);
+                        }
+                        a += sampled_pairs<MODEL>(R[w], sz, p, pz, valid, full);
+                    }
                 }
-                acc += sampled_pairs<MODEL>(R[w], sz, p, pz, valid, full);
             }
-            const int s2 = wave_sum_i32(acc);
-            if (lane == 0) sums[k] += s2;
+            a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xF, 0xF, true);   // row_shr:1
+            a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xF, 0xF, true);   // row_shr:2
+            a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xF, 0xF, true);   // row_shr:4
+            a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xF, 0xF, true);   // row_shr:8
+            if ((lane & 15) == 15) atomicAdd(&sums[k], a);
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nr; k += blockDim.x)
-        if (sums[k] != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)(int64_t)sums[k]);
+    // Ising from L = 512 on: the sums are differing bits (32 pairs a word)
+    for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+        if (sx_row((uint32_t)rl[k] & 15u, rho0, G) < 0) continue;
+        const int64_t v = diff_only ? 32 * (int64_t)NSW * rows_done - 2 * (int64_t)sums[k] : (int64_t)sums[k];
+        if (v != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)v);
+    }
 }
 
 // Along y: S_y(r) = sum over the sampled rows b and words k of the pairs of
@@ -1266,9 +1324,10 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
     constexpr int NB = MODEL == 1 ? 2 : 1;
     // along x: LDS holds the distance sums of a launch (8 bytes each: the sum
-    // and the distance), the source row and G residue rows of bits
-    const size_t rowb = (size_t)NB * tbits_words(L) * 4, budget = sx_lds_budget();
-    const uint32_t gx = grid_cap(std::min<uint32_t>(NS, 512));
+    // and the distance), the source row and G residue rows of bits, each row
+    // stored twice
+    const size_t rowb = (size_t)NB * 2 * tbits_words(L) * 4, budget = sx_lds_budget();
+    const uint32_t gx = grid_cap(std::min<uint32_t>(NS, 1024));
     uint32_t G = 16;
     while (G > 1 && 8u * 64u + rowb * (1 + G) > budget) G >>= 1;
     if (rowb * (1 + G) + 8 > budget) return hipErrorInvalidValue;
@@ -1284,7 +1343,7 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
         for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
-            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(1024), lds, s, g.plane0, L, a.r + j0, nr, rho0,
+            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(512), lds, s, g.plane0, L, a.r + j0, nr, rho0,
                                G, a.Cx + j0);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
