@@ -422,7 +422,7 @@ constexpr int kTileRows = kTH + kHalo;
 
 // Tile columns: the strip's words 0 .. kSW - 1 at CO .. CO + kSW - 1, the
 // word right of the strip after them, and with LEFT (CO = 1) the word left
-// of it at column 0.
+// of it at column 0 (of which only the last cell is loaded).
 template <int MODEL, bool LEFT>
 struct ShortTile {
     static constexpr int NB = MODEL == 1 ? 2 : 1;   // bit planes: sign [, nonzero]
@@ -495,6 +495,23 @@ __device__ __forceinline__ void tile_load(TT& T, const uint32_t* __restrict__ pl
         }
         y += step;
         if (y >= L) y -= L;
+    }
+}
+
+// Column 0 of tile row `row` (lattice word column qq) of both planes, for
+// 4-bit cells: the B/M/Q work uses only its last cell (the i - 1 neighbour
+// of the strip's cell 0), so one 4-byte load of the vector's last word gives
+// it (cell 31 is nibble 7 of that word, its sign bit bit 29).
+template <class TT>
+__device__ __forceinline__ void tile_load_left(TT& T, const uint4* __restrict__ P4, size_t plane_units, uint32_t Wp,
+                                               uint32_t L, uint32_t y0, uint32_t row, uint32_t qq)
+{
+    uint32_t y = y0 + row;
+    if (y >= L) y -= L;
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(P4 + c * plane_units + (size_t)y * Wp + qq)[3];
+        T.v[c][0][row][0] = ((w >> 29) & 1u) << 31;
     }
 }
 
@@ -688,8 +705,7 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x, kTileRows, kSW + CO,
                              wrap_col(q0 + kSW, Wp), bad);
         else if (FUSED && threadIdx.x >= 128 && threadIdx.x - 128 < kTileRows - row0)
-            tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + threadIdx.x - 128, kTileRows, 0,
-                             (q0 + Wp - 1) % Wp, bad);
+            tile_load_left(T, P4, plane_units, Wp, L, y0, row0 + threadIdx.x - 128, (q0 + Wp - 1) % Wp);
         __syncthreads();
         if (q0 + (uint32_t)j < Wp) {
             if (axis == 0) short_tile<MODEL, 0>(T, j, g, R, cacc);
@@ -1127,7 +1143,12 @@ __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restric
     }
     int words = 0;                                        // source words taken by this thread
     const uint32_t pairs = NS * groups;
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += gridDim.x * blockDim.x) {
+    // workgroup ids go round-robin to the 8 XCDs: XCD x takes the x-th eighth
+    // of the source rows, so neighbouring source rows (whose partner rows at
+    // nearby distances coincide) meet in the same L2
+    const uint32_t nb = gridDim.x;
+    const uint32_t bx = (nb & 7u) == 0 ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    for (uint32_t p = bx * blockDim.x + threadIdx.x; p < pairs; p += gridDim.x * blockDim.x) {
         const uint32_t b = p >> g_log, w = (p & (groups - 1)) * WPT;
         const uint32_t y = 16 * b;
         uint32_t s[WPT], sz[WPT];
