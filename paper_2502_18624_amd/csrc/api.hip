@@ -1059,6 +1059,7 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
             sa.Cx = h->Cx + n_all;
             sa.Cy = h->Cy + n_all;
             sa.tbits = h->tbits;
+            if (fused) sa.rbits = h->tbits + h->L * mcl::tbits_words(h->L);
             MCL_HIP(mcl::launch_corr_sampled(h->g, h->model, sa, h->stream));
         }
     }

@@ -56,14 +56,19 @@ hipError_t launch_zero(int64_t* p, int64_t n, hipStream_t s);
 // plane of [s != 0] after L rows); tbits_words(L) words per row, the L / 16
 // bits of a row repeated to fill one word below L = 512 (L is a power of
 // two wherever they are used; other L get room for ceil(L / 512) words).
+// 4-bit Ising lattices have room after the L rows for the residue rows of
+// the sampled rows: row 16 b + rho holds, for y = 16 b, bit j of word k =
+// [s(16 (32 k + j) + rho, y) = +1] (written by the fused short-distance
+// tiles, read by the sampled x pass).
 inline int64_t tbits_words(int64_t L) { return L >= 512 ? (L + 511) / 512 : 1; }
-inline int64_t tbits_bytes(int model, int64_t L) { return (model == 1 ? 2 : 1) * L * tbits_words(L) * 4; }
+inline int64_t tbits_bytes(int model, int64_t L) { return (model == 2 ? 1 : 2) * L * tbits_words(L) * 4; }
 // B, M, Q, counts and the sigma-h histogram into acc; with tbits set, also
 // the T bits of every row (written by the same pass from L = 512 on).
 hipError_t launch_bmq(const Geom& g, int model, int64_t* acc, uint32_t* tbits, hipStream_t s);
 // Correlations from every source at r = 0..R (R <= 32), LDS-tiled.  With acc
 // set (4-bit Ising cells, L >= 4096, see bmq_fused) the same tiles give what
-// launch_bmq adds to acc, and with tbits set (L a power of two) the T bits;
+// launch_bmq adds to acc, and with tbits set (L a power of two) the T bits
+// and the residue rows of the sampled rows after them;
 // acc[14] then counts the workgroups that met a cell holding no spin, for
 // which the caller must run launch_bmq instead (acc zeroed, tbits null).
 hipError_t launch_corr_short(const Geom& g, int model, int R, int64_t* Cx, int64_t* Cy, int64_t* acc,
@@ -84,6 +89,7 @@ struct SampledArgs {
     int64_t* Cx;
     int64_t* Cy;
     const uint32_t* tbits;
+    const uint32_t* rbits = nullptr;    // residue rows (4-bit Ising, written by the fused tiles), or null
 };
 hipError_t launch_corr_sampled(const Geom& g, int model, const SampledArgs& a, hipStream_t s);
 

@@ -631,6 +631,35 @@ __device__ __forceinline__ void tile_bmq(const TT& T, uint32_t y0, uint32_t q0, 
     }
 }
 
+// The residue rows of the tile's sampled rows (y = 16 b: tile rows 16, 32,
+// 48, 64, as y0 is a multiple of 64): thread (plane c, row 16 (s + 1), word
+// j) takes the bits t, t + 8, t + 16, t + 24 of its word for t = 0 .. 7,
+// the cells 16 a + 2 t + c of the row (x = 2 i + c on even rows, i = 8 a + t),
+// and merges them over 8 lanes into word (q0 + j) / 8 of residue row
+// 16 b + 2 t + c, as for the T bits.  Protocol lattices only (L a power of
+// two >= 4096: every lane of the strip is in it).
+template <class TT>
+__device__ __forceinline__ void tile_residues(const TT& T, uint32_t y0, uint32_t q0, uint32_t L,
+                                              uint32_t* __restrict__ rb)
+{
+    const uint32_t NSW = L >> 9;
+    const uint32_t c = threadIdx.x >> 7, r = 16 * (((threadIdx.x >> 5) & 3u) + 1);
+    const uint32_t j = threadIdx.x & 31u;
+    const uint32_t word = T.v[c][0][r][j + TT::CO];
+    uint32_t y = y0 + r;
+    if (y >= L) y -= L;
+    uint32_t* row = rb + (size_t)y * NSW + ((q0 + j) >> 3);       // y = 16 b: residue row 16 b + rho
+#pragma unroll 1
+    for (uint32_t t = 0; t < 8; ++t) {
+        const uint32_t x = (word >> t) & 0x01010101u;
+        uint32_t w = ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu) << (4 * (j & 7));
+        w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x111, 0xF, 0xF, true);   // row_shr:1
+        w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x112, 0xF, 0xF, true);   // row_shr:2
+        w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x114, 0xF, 0xF, true);   // row_shr:4
+        if ((j & 7) == 7) row[(size_t)(2 * t + c) * NSW] = w;
+    }
+}
+
 // Persistent over tiles: each workgroup loads tiles (strip of kSW words by
 // kTH rows, both planes, with halos) in turn and keeps its per-distance sums
 // in registers; one atomic per value per workgroup at the end.  FUSED (4-bit
@@ -712,7 +741,10 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
             else short_tile<MODEL, 1>(T, j, g, R, cacc);
             pairs += 16 * kTH;     // kTH / 4 rows x 2 planes x 32 cells, per distance
         }
-        if constexpr (FUSED) tile_bmq<MODEL>(T, y0, q0, L, Wp, j, tb, hist, np1, sites);
+        if constexpr (FUSED) {
+            tile_bmq<MODEL>(T, y0, q0, L, Wp, j, tb, hist, np1, sites);
+            if (tb) tile_residues(T, y0, q0, L, tb + (size_t)L * (L >> 9));
+        }
     }
     int64_t v[66];
 #pragma unroll
@@ -871,7 +903,9 @@ __global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__
 // k = w, w + n, ...: per row each lane sums its words, four DPP adds sum 16
 // lanes and the lanes 15, 31, 47, 63 add those to the distance's LDS sum.
 // Workgroups of 512 threads, several per CU, so one loads its next row
-// while another works on its own.
+// while another works on its own.  For 4-bit Ising lattices measured with
+// the fused short-distance tiles (rb set) the residue rows come ready from
+// those tiles, and the row's 4-bit cells are not read at all.
 //
 // Building the residue rows (L >= 512): a 4-bit word w of plane c holds the
 // cells x = 16 w + 2 j + c, j = 0 .. 7, i.e. bit w of residues 2 j + c, so a
@@ -887,7 +921,8 @@ __device__ __forceinline__ int sx_row(uint32_t rho, uint32_t rho0, uint32_t G)
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restrict__ planes, uint32_t L,
+__global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restrict__ planes,
+                                                      const uint32_t* __restrict__ rb, uint32_t L,
                                                        const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
                                                        uint32_t G, int64_t* __restrict__ Cx)
 {
@@ -917,7 +952,32 @@ __global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restric
         const uint32_t y = 16 * b;
         ++rows_done;
         __syncthreads();
-        if (L < 512) {
+        if (MODEL == 0 && rb != nullptr) {
+            // the residue rows the fused short-distance tiles wrote: row 0 the
+            // sources (residue 0), rows 1 .. G the residues rho0 .., each
+            // stored twice; kSxU loads in flight per thread
+            const uint32_t* src = rb + (size_t)y * NSW;   // residue row 16 b + rho at src + rho NSW
+            const uint32_t total = (1 + G) * NSW;
+            for (uint32_t base = threadIdx.x; base < total; base += kSxU * blockDim.x) {
+                uint32_t v[kSxU];
+#pragma unroll
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t t = base + u * blockDim.x;
+                    const uint32_t rr = t / NSW, w = t - rr * NSW;
+                    const uint32_t rho = rr == 0 ? 0u : rho0 + rr - 1;
+                    v[u] = t < total ? src[(size_t)rho * NSW + w] : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kSxU; ++u) {
+                    const uint32_t t = base + u * blockDim.x;
+                    if (t < total) {
+                        const uint32_t rr = t / NSW, w = t - rr * NSW;
+                        R[rr * rowstride + w] = v[u];
+                        R[rr * rowstride + NSW + w] = v[u];
+                    }
+                }
+            }
+        } else if (L < 512) {
             // one word per residue row, its NS bits repeated
             for (uint32_t t = threadIdx.x; t < (1 + G) * NB; t += blockDim.x) {
                 const uint32_t rr = t / NB, plane = t - rr * NB;
@@ -1046,8 +1106,8 @@ __global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restric
             }
         }
         __syncthreads();
-        // the second copy of each residue row
-        for (uint32_t t = threadIdx.x; t < G * NB * NSW; t += blockDim.x) {
+        // the second copy of each residue row (the packed rows come with it)
+        for (uint32_t t = threadIdx.x; !(MODEL == 0 && rb != nullptr) && t < G * NB * NSW; t += blockDim.x) {
             const uint32_t rr = 1 + t / (NB * NSW), rest = t % (NB * NSW);
             const uint32_t pl = rest / NSW, w = rest - pl * NSW;
             uint32_t* row = R + rr * rowstride + pl * PO;
@@ -1343,6 +1403,7 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
     const uint32_t L = (uint32_t)g.L, NS = L / 16;
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
+    if (a.rbits && (MODEL != 0 || L < 4096)) return hipErrorInvalidValue;
     constexpr int NB = MODEL == 1 ? 2 : 1;
     // along x: LDS holds the distance sums of a launch (8 bytes each: the sum
     // and the distance), the source row and G residue rows of bits, each row
@@ -1364,7 +1425,7 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
         for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
-            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(512), lds, s, g.plane0, L, a.r + j0, nr, rho0,
+            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(512), lds, s, g.plane0, a.rbits, L, a.r + j0, nr, rho0,
                                G, a.Cx + j0);
             e = hipGetLastError();
             if (e != hipSuccess) return e;

@@ -72,6 +72,7 @@ def test_footprint_covers_the_planes(mcl, model, m):
     bits = 1 if model == 2 else 4
     nb = mcl.query_bytes(model, L)
     # both planes and the bits of the sampled columns (two bit planes for
-    # Blume-Capel), ceil(L / 512) words a row
-    base = L * L * bits // 8 + (2 if model == 1 else 1) * L * 4 * max(1, -(-L // 512))
+    # Blume-Capel; for 4-bit Ising room for the residue rows of the sampled
+    # rows besides), ceil(L / 512) words a row
+    base = L * L * bits // 8 + (1 if model == 2 else 2) * L * 4 * max(1, -(-L // 512))
     assert base <= nb <= base + 64 * L + 8192 + (32768 if model == 2 else 0)
