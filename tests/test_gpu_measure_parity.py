@@ -172,3 +172,29 @@ def test_parity_size_quench_in_full(mcl):
         assert m["t"] == t
         _compare(m, s, oracle.CORR_FULL, 1)
     assert np.array_equal(lat.read(), s)
+
+
+@pytest.mark.parametrize("seed", [4700])
+def test_fused_tiles_on_a_partial_strip(mcl, monkeypatch, seed):
+    """Ising L = 4160 (65 words of a plane row: two strips of 32 words and
+    one of a single word), FULL correlations: the short-distance tiles give
+    the B/M/Q sums with a partial last strip and no T bits.  B, M, Q, the
+    counts and the histogram equal the oracle's, and every sum equals the
+    one with the separate B/M/Q pass (MCL_MEASURE_FUSED=0)."""
+    print("fused tiles on a partial strip", seed, flush=True)
+    L = 4160
+    lat = mcl.Lattice(mcl.ISING, L, seed)
+    lat.sweep(2, BETA_C)
+    m = lat.measure(mcl.CORR_FULL)
+    s = lat.read()
+    om = oracle.measure(s, _threads())
+    assert (m["B"], m["M"], m["Q"]) == (om["B"], om["M"], om["Q"])
+    assert m["counts"] == om["counts"] and m["invalid"] == 0
+    assert m["sd"] == [int(v) for v in oracle.sd_hist(s, _threads())]
+    monkeypatch.setenv("MCL_MEASURE_FUSED", "0")
+    m2 = lat.measure(mcl.CORR_FULL)
+    for k in ("B", "M", "Q", "counts", "sd"):
+        assert m2[k] == m[k], k
+    for k in ("r", "Cx", "Cy", "nsrc"):
+        assert np.array_equal(m2[k], m[k]), k
+    lat.free()
