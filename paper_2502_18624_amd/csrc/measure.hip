@@ -664,9 +664,11 @@ __device__ __forceinline__ void tile_residues(const TT& T, uint32_t y0, uint32_t
 // kTH rows, both planes, with halos) in turn and keeps its per-distance sums
 // in registers; one atomic per value per workgroup at the end.  FUSED (4-bit
 // Ising cells, L >= 4096): the tiles also give B, M, the counts, the sigma-h
-// histogram and the T bits (tile_bmq), so the B/M/Q pass need not read the
-// lattice again; acc[14] counts the workgroups that saw a cell holding no
-// spin, for which the caller runs the B/M/Q pass after all.
+// histogram and the T bits (tile_bmq) and the residue rows of the sampled
+// rows after the T bits (tile_residues), so the B/M/Q pass need not read the
+// lattice again and the sampled x pass reads packed rows; acc[14] counts the
+// workgroups that saw a cell holding no spin, for which the caller runs the
+// B/M/Q pass after all.
 template <int MODEL, bool FUSED>
 __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restrict__ planes, uint32_t L, int R,
                                                          int64_t* __restrict__ Cx, int64_t* __restrict__ Cy,
@@ -726,7 +728,8 @@ __global__ __launch_bounds__(256) void corr_short_kernel(const uint32_t* __restr
         const uint32_t row0 = reuse ? (uint32_t)kHalo : 0u;
         // the new rows: lane (column lc, row group lg) takes column lc of rows
         // row0 + lg, row0 + lg + 8, ...; then one thread per row each halo
-        // column (the words left and right of the strip, periodic in the row)
+        // column (the word right of the strip and, fused, the last cell of
+        // the word left of it, periodic in the row)
         const uint32_t lc = threadIdx.x & (kSW - 1), lg = threadIdx.x >> 5;
         tile_load<MODEL>(T, planes, P4, plane_units, Wp, L, y0, row0 + lg, blockDim.x / kSW, lc + CO,
                          wrap_col(q0 + lc, Wp), bad);
