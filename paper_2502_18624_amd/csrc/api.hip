@@ -30,6 +30,11 @@ struct mcl_lattice {
     uint32_t* tdev;      // device: sweep index at the start of a replayed graph
     int64_t rcap;
     hipStream_t stream;
+    // measure() of 1-bit lattices: the sampled y pass runs on `side` (created
+    // at the first measurement with sampled distances), between the events
+    // `fork` (the T bits are written) and `join` (before the results are read)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // executable graphs of kGraphSweeps sweeps, one per (beta, D) in use
     struct SweepGraph {
         double beta, D;
@@ -992,6 +997,9 @@ int lattice_free(mcl_lattice* h)
     // let it finish before the caller can reuse the buffer or the graphs go
     (void)hipStreamSynchronize(h->stream);                 // best effort: the handle goes either way
     for (const auto& sg : h->graphs) (void)hipGraphExecDestroy(sg.exec);
+    if (h->side) (void)hipStreamDestroy(h->side);           // idle: measure() joins it before returning
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    if (h->join) (void)hipEventDestroy(h->join);
     delete h;
     return MCL_OK;
 }
@@ -1044,7 +1052,32 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
     // read once; cells that hold no spin set acc[14], and then the B/M/Q pass
     // runs after all (below)
     const bool fused = nr > 0 && mcl::bmq_fused(h->g, h->model);
+    mcl::SampledArgs sa;
+    sa.r = h->rdev + n_all;
+    sa.nr = ns;
+    sa.Cx = h->Cx + n_all;
+    sa.Cy = h->Cy + n_all;
+    sa.tbits = h->tbits;
+    if (fused) sa.rbits = h->tbits + h->L * mcl::tbits_words(h->L);
+    // 1-bit lattices: the sampled y pass, which reads only the T bits and is
+    // bound by cache reads, runs on the side stream as soon as the B/M/Q pass
+    // has written them, beside the short-distance tiles, which are bound by
+    // VALU issue.  For 4-bit cells it overlaps worse (Blume-Capel's tiles hold
+    // fewer waves, and the fused Ising path has only the sampled x pass left
+    // to run beside it), so there everything stays on the lattice's stream.
+    const bool side_y = ns > 0 && h->model == MCL_ISING_LUT;
+    if (side_y && !h->side) {
+        MCL_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        MCL_HIP(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+        MCL_HIP(hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
+    }
     if (!fused) MCL_HIP(mcl::launch_bmq(h->g, h->model, h->acc, ns > 0 ? h->tbits : nullptr, h->stream));
+    if (side_y) {
+        MCL_HIP(hipEventRecord(h->fork, h->stream));
+        MCL_HIP(hipStreamWaitEvent(h->side, h->fork, 0));
+        MCL_HIP(mcl::launch_corr_sampled_y(h->g, h->model, sa, h->side));
+        MCL_HIP(hipEventRecord(h->join, h->side));
+    }
     if (nr > 0) {
         // every-source distances are r = 0 .. n_all - 1 (position j holds r = j)
         const int rshort = std::min(n_all - 1, 32);
@@ -1053,14 +1086,11 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
         if (n_all - 1 > 32)
             MCL_HIP(mcl::launch_corr_all(h->g, h->rdev + 33, n_all - 33, h->Cx + 33, h->Cy + 33, h->stream));
         if (ns > 0) {
-            mcl::SampledArgs sa;
-            sa.r = h->rdev + n_all;
-            sa.nr = ns;
-            sa.Cx = h->Cx + n_all;
-            sa.Cy = h->Cy + n_all;
-            sa.tbits = h->tbits;
-            if (fused) sa.rbits = h->tbits + h->L * mcl::tbits_words(h->L);
-            MCL_HIP(mcl::launch_corr_sampled(h->g, h->model, sa, h->stream));
+            MCL_HIP(mcl::launch_corr_sampled_x(h->g, h->model, sa, h->stream));
+            if (side_y)
+                MCL_HIP(hipStreamWaitEvent(h->stream, h->join, 0));
+            else
+                MCL_HIP(mcl::launch_corr_sampled_y(h->g, h->model, sa, h->stream));
         }
     }
     int64_t acc[mcl::kAccSlots];

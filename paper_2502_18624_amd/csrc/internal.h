@@ -91,7 +91,11 @@ struct SampledArgs {
     const uint32_t* tbits;
     const uint32_t* rbits = nullptr;    // residue rows (4-bit Ising, written by the fused tiles), or null
 };
-hipError_t launch_corr_sampled(const Geom& g, int model, const SampledArgs& a, hipStream_t s);
+// The sampled sources' two passes: x (the lattice's sampled rows, or the
+// residue rows when rbits is set) and y (the T bits only).  They are
+// independent, so the caller may run them on two streams.
+hipError_t launch_corr_sampled_x(const Geom& g, int model, const SampledArgs& a, hipStream_t s);
+hipError_t launch_corr_sampled_y(const Geom& g, int model, const SampledArgs& a, hipStream_t s);
 
 // Batched half-sweep.  One descriptor per replica (64 bytes).  The work of
 // a launch is a list of tiles of 256 threads; replica i owns the tiles

@@ -1402,7 +1402,7 @@ size_t sx_lds_budget()
 }
 
 template <int MODEL>
-hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
+hipError_t corr_sampled_x(const Geom& g, const SampledArgs& a, hipStream_t s)
 {
     const uint32_t L = (uint32_t)g.L, NS = L / 16;
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
@@ -1434,6 +1434,14 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
     }
+    return hipSuccess;
+}
+
+template <int MODEL>
+hipError_t corr_sampled_y(const Geom& g, const SampledArgs& a, hipStream_t sy)
+{
+    const uint32_t L = (uint32_t)g.L, NS = L / 16;
+    if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;
     // along y: a group of 4 source-row words per thread from L = 2048 on (one
     // word below), a grid row per 32 distances
     const uint32_t wpt = tbits_words(L) >= 4 ? 4u : 1u;
@@ -1441,18 +1449,24 @@ hipError_t corr_sampled(const Geom& g, const SampledArgs& a, hipStream_t s)
     const uint32_t gyx = grid_cap((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((groups + 255) / 256, 2048)));
     const dim3 gy(gyx, (uint32_t)((a.nr + kYChunk - 1) / kYChunk));
     if (wpt == 4)
-        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 4>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 4>), gy, dim3(256), 0, sy, a.tbits, L, a.r, a.nr, a.Cy);
     else
-        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 1>), gy, dim3(256), 0, s, a.tbits, L, a.r, a.nr, a.Cy);
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 1>), gy, dim3(256), 0, sy, a.tbits, L, a.r, a.nr, a.Cy);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_corr_sampled(const Geom& g, int model, const SampledArgs& a, hipStream_t s)
+hipError_t launch_corr_sampled_x(const Geom& g, int model, const SampledArgs& a, hipStream_t s)
 {
     if (a.nr <= 0) return hipSuccess;
-    return model == 2 ? corr_sampled<2>(g, a, s) : model == 1 ? corr_sampled<1>(g, a, s) : corr_sampled<0>(g, a, s);
+    return model == 2 ? corr_sampled_x<2>(g, a, s) : model == 1 ? corr_sampled_x<1>(g, a, s) : corr_sampled_x<0>(g, a, s);
+}
+
+hipError_t launch_corr_sampled_y(const Geom& g, int model, const SampledArgs& a, hipStream_t s)
+{
+    if (a.nr <= 0) return hipSuccess;
+    return model == 2 ? corr_sampled_y<2>(g, a, s) : model == 1 ? corr_sampled_y<1>(g, a, s) : corr_sampled_y<0>(g, a, s);
 }
 
 }  // namespace mcl
