@@ -902,11 +902,14 @@ __global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__
 // shift, one xor and the bit counts.  LDS holds R_0 and the residues rho0 ..
 // rho0 + G - 1 (the host runs 16 / G passes when a row of all 16 residues
 // does not fit), each residue row twice in a row, so the partner words
-// w + m / 32 and the next need no wrap.  Wave w of n owns the distances
-// k = w, w + n, ...: per row each lane sums its words, four DPP adds sum 16
-// lanes and the lanes 15, 31, 47, 63 add those to the distance's LDS sum.
-// Workgroups of 512 threads, several per CU, so one loads its next row
-// while another works on its own.  For 4-bit Ising lattices measured with
+// w + m / 32 and the next need no wrap, and two words of padding after each
+// row, so the rows of different residues start in different LDS banks.
+// Thread k owns distance k of the launch (the host gives a launch at most
+// one distance per thread): it walks every word of the row, reading the
+// source words as broadcast 16-byte loads, and keeps its sum in a register
+// over all the workgroup's rows; one atomic per distance and workgroup at
+// the end.  Workgroups of 512 threads, several per CU, so one loads its next
+// row while another works on its own.  For 4-bit Ising lattices measured with
 // the fused short-distance tiles (rb set) the residue rows come ready from
 // those tiles, and the row's 4-bit cells are not read at all.
 //
@@ -917,6 +920,7 @@ __global__ __launch_bounds__(256) void tbits_kernel(const uint32_t* __restrict__
 // residue 2 (k & 7) + c at position 4 w + (k >> 3), four bits per residue,
 // gathered per lane and merged over 8 lanes.
 constexpr uint32_t kSxU = 4;        // row loads in flight per thread
+constexpr int kSxThreads = 512;     // threads of a workgroup, and distances of a launch
 
 __device__ __forceinline__ int sx_row(uint32_t rho, uint32_t rho0, uint32_t G)
 {
@@ -924,7 +928,7 @@ __device__ __forceinline__ int sx_row(uint32_t rho, uint32_t rho0, uint32_t G)
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restrict__ planes,
+__global__ __launch_bounds__(kSxThreads) void corr_sxb_kernel(const uint32_t* __restrict__ planes,
                                                       const uint32_t* __restrict__ rb, uint32_t L,
                                                        const int32_t* __restrict__ rlist, int nr, uint32_t rho0,
                                                        uint32_t G, int64_t* __restrict__ Cx)
@@ -932,13 +936,11 @@ __global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restric
     constexpr int NB = MODEL == 1 ? 2 : 1;
     using C = Cell<MODEL == 2 ? 1 : 4>;
     extern __shared__ int sxb_lds[];
-    int* sums = sxb_lds;
-    int* rl = sxb_lds + nr;
-    uint32_t* R = reinterpret_cast<uint32_t*>(sxb_lds + 2 * nr);    // [(1 + G) rows][NB][2 NSW]
+    uint32_t* R = reinterpret_cast<uint32_t*>(sxb_lds);   // [(1 + G) rows][NB][2 NSW], + 2 words a row
     const uint32_t W = L >> C::kWordShift, NS = L >> 4;
     const uint32_t NSW = L >= 512 ? L >> 9 : 1u;
     const uint32_t PO = 2 * NSW;                          // bit plane offset within a row
-    const uint32_t rowstride = NB * PO;
+    const uint32_t rowstride = NB * PO + 2;
     const bool full = L >= 512;
     // Ising rows without invalid bits: a word's sum is 32 - 2 (differing bits)
     const bool diff_only = MODEL != 1 && full;
@@ -946,10 +948,13 @@ __global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restric
     const size_t plane_words = (size_t)L * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nwaves = blockDim.x >> 6;
-    for (int k = threadIdx.x; k < nr; k += blockDim.x) {
-        sums[k] = 0;
-        rl[k] = rlist[k];
-    }
+    // this thread's distance: r = 16 m + rho, the partners R_rho shifted by m
+    const int k = threadIdx.x;
+    const uint32_t r = k < nr ? (uint32_t)rlist[k] : 0u;
+    const int rr = k < nr ? sx_row(r & 15u, rho0, G) : -1;     // -1: none, or another pass's residue
+    const uint32_t m = r >> 4, sh = m & 31u;
+    const uint32_t poff = (rr < 0 ? 0u : (uint32_t)rr * rowstride) + (m >> 5);
+    uint32_t acc = 0;
     uint32_t rows_done = 0;
     for (uint32_t b = blockIdx.x; b < NS; b += gridDim.x) {
         const uint32_t y = 16 * b;
@@ -1117,42 +1122,37 @@ __global__ __launch_bounds__(512) void corr_sxb_kernel(const uint32_t* __restric
             row[NSW + w] = row[w];
         }
         __syncthreads();
-        for (int k = wave; k < nr; k += nwaves) {
-            const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane(rl[k]);
-            const int rr = sx_row(r & 15u, rho0, G);
-            if (rr < 0) continue;                                 // another pass's residue
-            const uint32_t m = r >> 4;
-            const uint32_t* P = R + rr * rowstride + (m >> 5);
-            const uint32_t sh = m & 31u;
-            int a = 0;
-            for (uint32_t w0 = 0; w0 < NSW; w0 += 64) {
-                const uint32_t w = w0 + (uint32_t)lane;
-                if (w < NSW) {
+        if (rr >= 0) {
+            const uint32_t* P = R + poff;
+            if (diff_only && (NSW & 3u) == 0) {
+                for (uint32_t w = 0; w < NSW; w += 4) {
+                    const uint4 s4 = *reinterpret_cast<const uint4*>(R + w);
+                    const uint32_t p0 = P[w], p1 = P[w + 1], p2 = P[w + 2], p3 = P[w + 3], p4 = P[w + 4];
+                    acc = bcnt_acc(s4.x ^ funnel(p1, p0, sh), acc);
+                    acc = bcnt_acc(s4.y ^ funnel(p2, p1, sh), acc);
+                    acc = bcnt_acc(s4.z ^ funnel(p3, p2, sh), acc);
+                    acc = bcnt_acc(s4.w ^ funnel(p4, p3, sh), acc);
+                }
+            } else {
+                for (uint32_t w = 0; w < NSW; ++w) {
                     const uint32_t p = funnel(P[w + 1], P[w], sh);
                     if (diff_only) {
-                        a = (int)bcnt_acc(R[w] ^ p, (uint32_t)a);
+                        acc = bcnt_acc(R[w] ^ p, acc);
                     } else {
                         uint32_t sz = 0, pz = 0;
                         if (NB == 2) {
                             sz = R[PO + w];
                             pz = funnel(P[PO + w + 1], P[PO + w], sh);
                         }
-                        a += sampled_pairs<MODEL>(R[w], sz, p, pz, valid, full);
+                        acc += (uint32_t)sampled_pairs<MODEL>(R[w], sz, p, pz, valid, full);
                     }
                 }
             }
-            a += __builtin_amdgcn_update_dpp(0, a, 0x111, 0xF, 0xF, true);   // row_shr:1
-            a += __builtin_amdgcn_update_dpp(0, a, 0x112, 0xF, 0xF, true);   // row_shr:2
-            a += __builtin_amdgcn_update_dpp(0, a, 0x114, 0xF, 0xF, true);   // row_shr:4
-            a += __builtin_amdgcn_update_dpp(0, a, 0x118, 0xF, 0xF, true);   // row_shr:8
-            if ((lane & 15) == 15) atomicAdd(&sums[k], a);
         }
     }
-    __syncthreads();
-    // Ising from L = 512 on: the sums are differing bits (32 pairs a word)
-    for (int k = threadIdx.x; k < nr; k += blockDim.x) {
-        if (sx_row((uint32_t)rl[k] & 15u, rho0, G) < 0) continue;
-        const int64_t v = diff_only ? 32 * (int64_t)NSW * rows_done - 2 * (int64_t)sums[k] : (int64_t)sums[k];
+    // Ising from L = 512 on: the sum counts differing bits (32 pairs a word)
+    if (rr >= 0) {
+        const int64_t v = diff_only ? 32 * (int64_t)NSW * rows_done - 2 * (int64_t)acc : (int64_t)(int32_t)acc;
         if (v != 0) atomicAdd((unsigned long long*)&Cx[k], (unsigned long long)v);
     }
 }
@@ -1408,19 +1408,19 @@ hipError_t corr_sampled_x(const Geom& g, const SampledArgs& a, hipStream_t s)
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;   // the protocol's lattices only
     if (a.rbits && (MODEL != 0 || L < 4096)) return hipErrorInvalidValue;
     constexpr int NB = MODEL == 1 ? 2 : 1;
-    // along x: LDS holds the distance sums of a launch (8 bytes each: the sum
-    // and the distance), the source row and G residue rows of bits, each row
-    // stored twice
-    const size_t rowb = (size_t)NB * 2 * tbits_words(L) * 4, budget = sx_lds_budget();
+    // along x: LDS holds the source row and G residue rows of bits, each
+    // row stored twice and padded by two words; a launch takes one distance
+    // per thread
+    const size_t rowb = ((size_t)NB * 2 * tbits_words(L) + 2) * 4, budget = sx_lds_budget();
     const uint32_t gx = grid_cap(std::min<uint32_t>(NS, 1024));
     uint32_t G = 16;
-    while (G > 1 && 8u * 64u + rowb * (1 + G) > budget) G >>= 1;
-    if (rowb * (1 + G) + 8 > budget) return hipErrorInvalidValue;
-    const int max_r = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)budget - (int64_t)(rowb * (1 + G))) / 8));
+    while (G > 1 && rowb * (1 + G) > budget) G >>= 1;
+    if (rowb * (1 + G) > budget) return hipErrorInvalidValue;
+    const int max_r = kSxThreads;
     hipError_t e = hipSuccess;
     for (int j0 = 0; j0 < a.nr; j0 += max_r) {
         const int nr = std::min(max_r, a.nr - j0);
-        const size_t lds = (size_t)nr * 8 + rowb * (1 + G);
+        const size_t lds = rowb * (1 + G);
         // the attribute belongs to the current device: set it for every launch that needs it
         if (lds > 64u * 1024u) {
             e = hipFuncSetAttribute((const void*)corr_sxb_kernel<MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1428,7 +1428,7 @@ hipError_t corr_sampled_x(const Geom& g, const SampledArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
         }
         for (uint32_t rho0 = 0; rho0 < 16; rho0 += G) {
-            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(512), lds, s, g.plane0, a.rbits, L, a.r + j0, nr, rho0,
+            hipLaunchKernelGGL((corr_sxb_kernel<MODEL>), dim3(gx), dim3(kSxThreads), lds, s, g.plane0, a.rbits, L, a.r + j0, nr, rho0,
                                G, a.Cx + j0);
             e = hipGetLastError();
             if (e != hipSuccess) return e;

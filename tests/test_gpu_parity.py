@@ -253,15 +253,16 @@ def test_group_sweep_equals_plain(mcl):
         assert np.array_equal(lat.read(), _oracle_run(m, L, s, 0, n, b, D))
 
 
-@pytest.mark.parametrize("budget,model", [(900, 0), (800, 1), (900, 1), (900, 2), (700, 2), (700, 0)])
+@pytest.mark.parametrize("budget,model", [(500, 0), (200, 0), (500, 1), (300, 1), (500, 2), (200, 2)])
 def test_sampled_x_correlation_in_residue_passes(mcl, monkeypatch, budget, model):
     """The x-correlation of the sampled sources keeps the source row and a
     group of residue rows in LDS as bits; lattices whose rows do not fit
     (Blume-Capel at L = 2^20) take several passes.  Forcing a small LDS
-    budget runs that form at L = 4096 (rows of 64 bytes a bit plane, each
-    residue row stored twice; 900 bytes: 4 residues per pass for Ising, 2
-    for Blume-Capel; 800 for Blume-Capel and 700 for Ising: one) with the
-    distance list split over several launches, against the oracle."""
+    budget runs that form at L = 4096 (rows of 32 bytes a bit plane, each
+    residue row stored twice and padded by 8 bytes; 500 bytes: 4 residues
+    per pass for Ising, 2 for Blume-Capel; 200 for Ising and 300 for
+    Blume-Capel: one), against the oracle.  The distance list takes one
+    launch per 512 distances, several at t = 10^6 (below)."""
     print("sampled x in passes", budget, model, flush=True)
     monkeypatch.setenv("MCL_SX_LDS_BUDGET", str(budget))
     L = 4096
