@@ -1059,6 +1059,13 @@ int measure(mcl_lattice* h, int corr_mode, mcl_measure_out* out)
     sa.Cy = h->Cy + n_all;
     sa.tbits = h->tbits;
     if (fused) sa.rbits = h->tbits + h->L * mcl::tbits_words(h->L);
+    if (ns > 0) {
+        // the sampled distances start with a run of consecutive ones (the
+        // linear range up to r_c(t)), which the y pass takes apart
+        sa.rlin0 = (uint32_t)r[n_all];
+        sa.nlin = 1;
+        while (sa.nlin < ns && r[n_all + sa.nlin] == r[n_all] + sa.nlin) ++sa.nlin;
+    }
     // 1-bit lattices: the sampled y pass, which reads only the T bits and is
     // bound by cache reads, runs on the side stream as soon as the B/M/Q pass
     // has written them, beside the short-distance tiles, which are bound by

@@ -90,6 +90,8 @@ struct SampledArgs {
     int64_t* Cy;
     const uint32_t* tbits;
     const uint32_t* rbits = nullptr;    // residue rows (4-bit Ising, written by the fused tiles), or null
+    int nlin = 0;                       // r[0 .. nlin) = rlin0, rlin0 + 1, ... (consecutive distances)
+    uint32_t rlin0 = 0;
 };
 // The sampled sources' two passes: x (the lattice's sampled rows, or the
 // residue rows when rbits is set) and y (the T bits only).  They are

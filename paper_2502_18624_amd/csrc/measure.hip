@@ -1252,6 +1252,82 @@ __global__ __launch_bounds__(256) void corr_syb_kernel(const uint32_t* __restric
     }
 }
 
+// Along y, the sampled distances r0 .. r0 + nl - 1 that follow one another
+// (the protocol's linear range).  Source rows 16 b and 16 (b + 1) meet the
+// same partner rows at distances r + 16 and r, so a workgroup takes a band of
+// kYLRows source rows and stages their partner rows, 16 (kYLRows - 1) +
+// kYLDist consecutive T rows, in LDS, kYLWords words of each at a time (a
+// row of T words is a multiple of 8 from L = 4096 on; rows padded by one
+// vector); thread d owns distance r0 + kYLDist c + d (c the grid
+// row) and keeps its count in a register over the band and all columns.
+// Ising rows from L = 4096 on: no invalid bits, so a word's sum is 32 minus
+// twice its differing bits.
+constexpr int kYLRows = 16;
+constexpr int kYLDist = 256;
+constexpr int kYLWords = 8;
+constexpr int kYLVec = kYLWords / 4;                  // 16-byte vectors of a row's column
+constexpr int kYLTgt = 16 * (kYLRows - 1) + kYLDist;
+constexpr int kYLPad = kYLVec + 1;                    // 16-byte vectors per staged row
+
+__global__ __launch_bounds__(256) void corr_sylin_kernel(const uint32_t* __restrict__ tb, uint32_t L, uint32_t r0,
+                                                         int nl, int64_t* __restrict__ Cy)
+{
+    __shared__ uint4 tgt[kYLTgt * kYLPad];
+    __shared__ uint4 src[kYLRows * kYLVec];
+    const uint32_t NSW = L >> 9;
+    // bands in XCD-contiguous eighths (workgroup ids go round-robin to the
+    // XCDs), so neighbouring bands share their partner rows in one L2
+    const uint32_t nb = gridDim.x;
+    const uint32_t band = (nb & 7u) == 0 ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const uint32_t b0 = band * kYLRows;
+    const int c = blockIdx.y;
+    const uint32_t ra = r0 + (uint32_t)c * kYLDist;
+    const int nd = min(kYLDist, nl - c * kYLDist);
+    const uint32_t nvec = (16 * (kYLRows - 1) + (uint32_t)nd) * kYLVec;
+    const int d = threadIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t w0 = 0; w0 < NSW; w0 += kYLWords) {
+        __syncthreads();
+        // vector v: row v / kYLVec, words w0 + 4 (v % kYLVec) ..; 8 loads in flight
+        for (uint32_t base = threadIdx.x; base < nvec; base += 8 * blockDim.x) {
+            uint4 x[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                const uint32_t v = base + u * blockDim.x;
+                const uint32_t y = (16 * b0 + ra + v / kYLVec) & (L - 1);
+                x[u] = v < nvec ? *reinterpret_cast<const uint4*>(tb + (size_t)y * NSW + w0 + 4 * (v % kYLVec))
+                                : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                const uint32_t v = base + u * blockDim.x;
+                if (v < nvec) tgt[(v / kYLVec) * kYLPad + v % kYLVec] = x[u];
+            }
+        }
+        if (threadIdx.x < kYLRows * kYLVec) {
+            const uint32_t i = threadIdx.x / kYLVec, j = threadIdx.x % kYLVec;
+            src[threadIdx.x] = *reinterpret_cast<const uint4*>(tb + (size_t)(16 * (b0 + i)) * NSW + w0 + 4 * j);
+        }
+        __syncthreads();
+        if (d < nd) {
+            for (int i = 0; i < kYLRows; ++i) {
+#pragma unroll
+                for (int j = 0; j < kYLVec; ++j) {
+                    const uint4 a = src[i * kYLVec + j], t = tgt[(16 * i + d) * kYLPad + j];
+                    acc = bcnt_acc(a.x ^ t.x, acc);
+                    acc = bcnt_acc(a.y ^ t.y, acc);
+                    acc = bcnt_acc(a.z ^ t.z, acc);
+                    acc = bcnt_acc(a.w ^ t.w, acc);
+                }
+            }
+        }
+    }
+    if (d < nd) {
+        const int64_t v = (int64_t)32 * kYLRows * NSW - 2 * (int64_t)acc;
+        atomicAdd((unsigned long long*)&Cy[c * kYLDist + d], (unsigned long long)v);
+    }
+}
+
 int64_t pick_rows(int64_t L, int64_t want)
 {
     int64_t rows = want;
@@ -1442,16 +1518,28 @@ hipError_t corr_sampled_y(const Geom& g, const SampledArgs& a, hipStream_t sy)
 {
     const uint32_t L = (uint32_t)g.L, NS = L / 16;
     if ((L & (L - 1)) != 0 || L < 64) return hipErrorInvalidValue;
-    // along y: a group of 4 source-row words per thread from L = 2048 on (one
-    // word below), a grid row per 32 distances
+    // the consecutive distances first, for Ising from L = 4096 on: partner
+    // rows staged in LDS per band of source rows
+    int done = 0;
+    if (MODEL != 1 && L >= 4096 && a.nlin > 0) {
+        const dim3 gl(NS / kYLRows, (uint32_t)((a.nlin + kYLDist - 1) / kYLDist));
+        hipLaunchKernelGGL(corr_sylin_kernel, gl, dim3(kYLDist), 0, sy, a.tbits, L, a.rlin0, a.nlin, a.Cy);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        done = a.nlin;
+    }
+    const int nr = a.nr - done;
+    if (nr <= 0) return hipSuccess;
+    // the others: a group of 4 source-row words per thread from L = 2048 on
+    // (one word below), a grid row per 32 distances
     const uint32_t wpt = tbits_words(L) >= 4 ? 4u : 1u;
     const uint64_t groups = (uint64_t)NS * (tbits_words(L) / wpt);
     const uint32_t gyx = grid_cap((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((groups + 255) / 256, 2048)));
-    const dim3 gy(gyx, (uint32_t)((a.nr + kYChunk - 1) / kYChunk));
+    const dim3 gy(gyx, (uint32_t)((nr + kYChunk - 1) / kYChunk));
     if (wpt == 4)
-        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 4>), gy, dim3(256), 0, sy, a.tbits, L, a.r, a.nr, a.Cy);
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 4>), gy, dim3(256), 0, sy, a.tbits, L, a.r + done, nr, a.Cy + done);
     else
-        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 1>), gy, dim3(256), 0, sy, a.tbits, L, a.r, a.nr, a.Cy);
+        hipLaunchKernelGGL((corr_syb_kernel<MODEL, 1>), gy, dim3(256), 0, sy, a.tbits, L, a.r + done, nr, a.Cy + done);
     return hipGetLastError();
 }
 
