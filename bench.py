@@ -545,6 +545,7 @@ def run(args):
                    "L": L, "seed": seed, "beta": beta, "measure_times": marks},
         "sweep_only_updates_per_ns": round(updates / (sweep_ms * 1e6), 2),
         "measure_share": round(t_meas / wall, 4),
+        "measure_ms_avg": round(t_meas / len(measures) * 1e3, 3) if measures else None,
         "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "hbm_achieved_GBs": round(hbm_gbs, 1),
         "hbm_attainable_copy_GBs": attainable_copy(),
