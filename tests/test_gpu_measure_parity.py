@@ -198,3 +198,29 @@ def test_fused_tiles_on_a_partial_strip(mcl, monkeypatch, seed):
     for k in ("r", "Cx", "Cy", "nsrc"):
         assert np.array_equal(m2[k], m[k]), k
     lat.free()
+
+
+def test_one_bit_measurement_on_a_caller_stream(mcl):
+    """1-bit lattices run the sampled y pass on a second stream of the
+    handle, forked from and joined back into the lattice's stream.  A lattice
+    queued on a stream of the caller's measures the same sums as one on the
+    current stream, at sizes where the y pass covers the consecutive and the
+    log-spaced distances."""
+    import torch
+    print("1-bit measurement on a caller stream", flush=True)
+    L, seed = 8192, 4800
+    side = torch.cuda.Stream()
+    a = mcl.Lattice(mcl.ISING_LUT, L, seed, stream=side)
+    b = mcl.Lattice(mcl.ISING_LUT, L, seed)
+    for lat in (a, b):
+        lat.sweep(3, BETA_C)
+    ma, mb = a.measure(mcl.CORR_PROTOCOL), b.measure(mcl.CORR_PROTOCOL)
+    for k in ("B", "M", "Q", "counts", "sd", "t"):
+        assert ma[k] == mb[k], k
+    for k in ("r", "Cx", "Cy", "nsrc"):
+        assert np.array_equal(ma[k], mb[k]), k
+    s = b.read()
+    Cx, Cy, _ = oracle.corr(s, oracle.CORR_PROTOCOL, mb["r"], _threads())
+    assert np.array_equal(mb["Cy"], Cy) and np.array_equal(mb["Cx"], Cx)
+    a.free()
+    b.free()
